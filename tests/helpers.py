@@ -1,0 +1,179 @@
+"""Test-side helpers: brute-force references, dense Hamiltonians and exact MPS builders.
+
+These are independent routes used to pin the oracle: explicit index loops,
+Kronecker-product Hamiltonians written from Pauli strings, exact
+diagonalisation, and states whose energies are known in closed form.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# brute force contractions (pure Python loops, tiny sizes only)
+# --------------------------------------------------------------------------
+
+
+def brute_tensordot(a, b, axes_a, axes_b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    free_a = [i for i in range(a.ndim) if i not in axes_a]
+    free_b = [j for j in range(b.ndim) if j not in axes_b]
+    out_shape = [a.shape[i] for i in free_a] + [b.shape[j] for j in free_b]
+    kdims = [a.shape[i] for i in axes_a]
+    out = np.zeros(out_shape)
+    for oidx in itertools.product(*[range(s) for s in out_shape]):
+        ia = [0] * a.ndim
+        ib = [0] * b.ndim
+        for p, i in enumerate(free_a):
+            ia[i] = oidx[p]
+        for p, j in enumerate(free_b):
+            ib[j] = oidx[len(free_a) + p]
+        acc = 0.0
+        for kidx in itertools.product(*[range(s) for s in kdims]):
+            for p, (i, j) in enumerate(zip(axes_a, axes_b)):
+                ia[i] = kidx[p]
+                ib[j] = kidx[p]
+            acc += a[tuple(ia)] * b[tuple(ib)]
+        out[oidx] = acc
+    return out
+
+
+def brute_network(tensors, labels):
+    """Full sum over every connected label of the product of all entries (loops)."""
+    all_labels = sorted({x for l in labels for x in l})
+    dims = {}
+    for t, l in zip(tensors, labels):
+        for ax, x in enumerate(l):
+            dims[x] = t.shape[ax]
+    closed = [x for x in all_labels if x >= 0]
+    opened = sorted([x for x in all_labels if x < 0], reverse=True)  # -1, -2, ...
+    out = np.zeros([dims[x] for x in opened])
+    for oidx in itertools.product(*[range(dims[x]) for x in opened]):
+        assign = dict(zip(opened, oidx))
+        acc = 0.0
+        for cidx in itertools.product(*[range(dims[x]) for x in closed]):
+            assign.update(zip(closed, cidx))
+            prod = 1.0
+            for t, l in zip(tensors, labels):
+                prod *= t[tuple(assign[x] for x in l)]
+            acc += prod
+        out[oidx] = acc
+    return out
+
+
+# --------------------------------------------------------------------------
+# dense spin-chain Hamiltonians from Pauli strings
+# --------------------------------------------------------------------------
+
+PX = np.array([[0, 1], [1, 0]], dtype=complex)
+PY = np.array([[0, -1j], [1j, 0]], dtype=complex)
+PZ = np.array([[1, 0], [0, -1]], dtype=complex)
+I2 = np.eye(2, dtype=complex)
+
+
+def _site_op(op, i, n):
+    m = np.ones((1, 1), dtype=complex)
+    for k in range(n):
+        m = np.kron(m, op if k == i else I2)
+    return m
+
+
+def dense_tfim(n, J=1.0, g=1.0):
+    h = np.zeros((2 ** n, 2 ** n), dtype=complex)
+    for i in range(n - 1):
+        h -= J * _site_op(PZ, i, n) @ _site_op(PZ, i + 1, n)
+    for i in range(n):
+        h -= g * _site_op(PX, i, n)
+    return h.real
+
+
+def dense_xxz(n, delta):
+    h = np.zeros((2 ** n, 2 ** n), dtype=complex)
+    for i in range(n - 1):
+        for op, c in ((PX, 1.0), (PY, 1.0), (PZ, delta)):
+            h += c * 0.25 * _site_op(op, i, n) @ _site_op(op, i + 1, n)
+    assert np.abs(h.imag).max() < 1e-14
+    return h.real
+
+
+def tfim_ground_energy_closed_form(n):
+    """Open critical TFIM (J = g = 1): E0 = 1 - 1/sin(pi / (2 (2N + 1)))."""
+    return 1.0 - 1.0 / math.sin(math.pi / (2.0 * (2 * n + 1)))
+
+
+def xx_ground_energy_closed_form(n):
+    """XX chain (delta = 0): free fermions with levels cos(pi k/(N+1)); fill the negative ones."""
+    lv = [math.cos(math.pi * k / (n + 1)) for k in range(1, n + 1)]
+    return sum(x for x in lv if x < 0)
+
+
+# --------------------------------------------------------------------------
+# exact MPS builders
+# --------------------------------------------------------------------------
+
+
+def dense_to_mps(vec, n, d=2):
+    """Exact MPS of a dense state by successive SVDs (no truncation)."""
+    sites = []
+    rest = np.asarray(vec, dtype=np.float64).reshape(1, -1)
+    dl = 1
+    for k in range(n - 1):
+        m = rest.reshape(dl * d, -1)
+        u, s, vt = np.linalg.svd(m, full_matrices=False)
+        sites.append(u.reshape(dl, d, -1))
+        rest = s[:, None] * vt
+        dl = u.shape[1]
+    sites.append(rest.reshape(dl, d, 1))
+    return sites
+
+
+def random_orthogonal(n, rng):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def product_state_mps(local_vectors, dims, rng):
+    """Product state embedded in bond dims `dims` and hidden by random orthogonal gauges.
+
+    Site k carries the local vector in entry [0, :, 0] of a zero tensor of
+    shape [D_k, d, D_{k+1}]; then A_k <- G_k^T A_k G_{k+1} with random
+    orthogonal G_k (G_0 = G_N = [[1]]).  The state is unchanged, so its norm
+    and energies keep their closed forms while every entry becomes dense.
+    """
+    n = len(local_vectors)
+    d = len(local_vectors[0])
+    gs = [np.ones((1, 1))] + [random_orthogonal(dims[k], rng) for k in range(1, n)] + [np.ones((1, 1))]
+    sites = []
+    for k in range(n):
+        a = np.zeros((dims[k], d, dims[k + 1]))
+        a[0, :, 0] = local_vectors[k]
+        a = np.einsum("ia,asb,bj->isj", gs[k].T, a, gs[k + 1])
+        sites.append(a)
+    return sites
+
+
+def spin_angle_vector(theta):
+    """cos(theta/2)|0> + sin(theta/2)|1>: <Z> = cos(theta), <X> = sin(theta)."""
+    return np.array([math.cos(theta / 2), math.sin(theta / 2)])
+
+
+# --------------------------------------------------------------------------
+# error measures
+# --------------------------------------------------------------------------
+
+
+def rel_fro(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.linalg.norm(ref.ravel())
+    num = np.linalg.norm((x - ref).ravel())
+    return num / den if den > 0 else num
+
+
+def scalar_ms_rel(m, s, m_ref, s_ref):
+    """|m e^s / (m_ref e^s_ref) - 1| for (mantissa, log-scale) pairs."""
+    return abs(m / m_ref * math.exp(s - s_ref) - 1.0)
