@@ -1,0 +1,232 @@
+/*
+ * tn.h -- C ABI of the MI355X (gfx950) tensor-network contraction library.
+ *
+ * Operations follow "TensorNetwork: A Library for Physics and Machine
+ * Learning" (arXiv:1905.01330): pairwise contraction of connected edges
+ * (section III.A "Standard Edges", III.B "Edge Contraction", "Edge
+ * Flattening"), trace edges (III.A "Trace Edges"), outer products (III.B,
+ * the outer-product equation), ncon networks with a contraction order
+ * (Appendix B), and the chain networks of section IV (MPS inner products,
+ * operator environments, and the MPS classifier of section IV.A).
+ *
+ * Conventions for every call
+ *  - Tensor data pointers are DEVICE pointers owned by the caller.  The
+ *    library never allocates device memory: scratch comes from a caller
+ *    workspace whose size the matching *_workspace query returns.  Host
+ *    pointers (descriptors, axis lists, label lists) are read during the
+ *    call only.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*,
+ *    NULL = the default stream).  Outputs are valid once the stream reaches
+ *    the point after the call.
+ *  - Arguments are validated on the host before anything is launched.  An
+ *    invalid call returns a negative tn_status and has no side effects;
+ *    tn_last_error() then holds a one-line description (thread-local).
+ *  - NaN and Inf propagate through arithmetic; they are not errors.
+ *  - Real arithmetic only: conjugation is the identity.
+ *  - Calls on different streams may run concurrently; calls that write the
+ *    same workspace or output on overlapping streams race.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TN_MAX_RANK 8
+
+typedef enum { TN_F32 = 0, TN_F64 = 1 } tn_dtype;
+
+/* Arithmetic used for the contracted-index products.
+ *  FP32          FP32 operands, FP32 accumulation (matrix cores, fp32 MFMA).
+ *  BF16          operands rounded to BF16 (nearest-even), FP32 accumulation.
+ *  SPLIT_BF16    each FP32 operand written exactly as x0 + x1 + x2 (three
+ *                BF16 terms); the six products x_i*y_j with i + j <= 2 are
+ *                accumulated into one FP32 accumulator per output.
+ *  SPLIT_BF16_3P two-term split, three products (error reported only). */
+typedef enum {
+  TN_PREC_FP32 = 0,
+  TN_PREC_BF16 = 1,
+  TN_PREC_SPLIT_BF16 = 2,
+  TN_PREC_SPLIT_BF16_3P = 3
+} tn_precision;
+
+/* A strided view: element (i_0..i_{r-1}) lives at data + sum_k i_k*stride[k]
+ * elements.  rank 0 is a scalar (one element).  Every shape[k] >= 1 and
+ * every stride[k] >= 0.  dtype: TN_F32 for contractions, TN_F64 where stated. */
+typedef struct {
+  void* data;
+  int32_t dtype;
+  int32_t rank;
+  int64_t shape[TN_MAX_RANK];
+  int64_t stride[TN_MAX_RANK];
+} tn_tensor;
+
+typedef enum {
+  TN_OK = 0,
+  TN_ERR_INVALID_ARGUMENT = -1,   /* NULL pointer, rank or axis out of range, repeated axis */
+  TN_ERR_SHAPE_MISMATCH = -2,     /* connected dimensions differ, or output shape is wrong */
+  TN_ERR_UNSUPPORTED = -3,        /* dtype / precision / size not handled */
+  TN_ERR_WORKSPACE_TOO_SMALL = -4,
+  TN_ERR_ALIASING = -5,           /* output memory overlaps an input */
+  TN_ERR_DEVICE = -6              /* a HIP runtime call failed (also earlier asynchronous faults) */
+} tn_status;
+
+const char* tn_status_string(int32_t status);
+const char* tn_last_error(void);
+/* Library version string, e.g. "tn-mi355x 0.1 gfx950". */
+const char* tn_version(void);
+
+/* ---------------------------------------------------------------------
+ * Pairwise contraction (III.A "Standard Edges": a tensordot over the
+ * connected axes; III.B "Edge Flattening": all edges between the two nodes
+ * contracted at once, so the pairs form one flattened contracted index).
+ *
+ * out[free_a..., free_b...] = sum_k a[...] * b[...], with axes_a[i] of `a`
+ * connected to axes_b[i] of `b` for i < n_pairs.  out's axes are the free
+ * axes of a in ascending order, then those of b; out->shape must equal
+ * that exactly.  out->stride may be any permutation view, which is how a
+ * final reorder_edges is fused into the store.  n_pairs == 0 is an outer
+ * product.  a, b, out: TN_F32, and `out` may not overlap `a` or `b`.
+ * Rank-0 and rank-1 results use wavefront reductions; the rest is a tiled
+ * matrix-core GEMM whose operand gathers perform the index permutation.
+ * ------------------------------------------------------------------- */
+int32_t tn_contract_between(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs,
+                            const int32_t* axes_a, const int32_t* axes_b, tn_tensor* out,
+                            int32_t prec, void* stream);
+
+/* Trace edge (III.A "Trace Edges"; the trace of Fig. 2):
+ * out[rest] = sum_i a[.. i .. i ..] over axis1 and axis2 (equal dims),
+ * rest in ascending axis order.  TN_F32. */
+int32_t tn_trace_edge(const tn_tensor* a, int32_t axis1, int32_t axis2, tn_tensor* out,
+                      void* stream);
+
+/* Outer product (III.B, the outer-product equation):
+ * out[i..., j...] = a[i...] * b[j...]; out shape = a.shape ++ b.shape.  TN_F32. */
+int32_t tn_outer_product(const tn_tensor* a, const tn_tensor* b, tn_tensor* out, void* stream);
+
+/* ---------------------------------------------------------------------
+ * ncon network (Appendix B).  Node i has labels[offsets[i] .. offsets[i+1]),
+ * one per axis.  A label >= 0 is a connected edge and appears exactly twice
+ * (twice on one node = a trace edge); a label < 0 is dangling and the
+ * output axes are ordered -1, -2, -3, ...  `order` lists the connected
+ * labels in contraction order (n_order = 0 or order = NULL: ascending).
+ * Contracting a label between two nodes contracts every edge they share
+ * (flattening).  Nodes still unconnected at the end are joined by outer
+ * products in node order.  The final permutation is fused into the last
+ * step's store.  Intermediates live in `workspace` (FP32, caller-owned);
+ * tn_contract_network_workspace returns the bytes needed.
+ * ------------------------------------------------------------------- */
+int32_t tn_contract_network_workspace(int32_t n_nodes, const tn_tensor* nodes,
+                                      const int32_t* labels, const int32_t* offsets,
+                                      int32_t n_order, const int32_t* order, size_t* bytes);
+int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels,
+                            const int32_t* offsets, int32_t n_order, const int32_t* order,
+                            tn_tensor* out, void* workspace, size_t ws_bytes, int32_t prec,
+                            void* stream);
+
+/* ---------------------------------------------------------------------
+ * MPS inner product <psi|phi> (the chain network of Fig. 3a, contracted
+ * site by site from the left).  psi[k], phi[k] are TN_F32 [D_k, d, D_{k+1}]
+ * with D_0 = D_N = 1 (the two chains may have different bond dims but the
+ * same d).  Result written to out2 (DEVICE, 2 doubles): out2[0] = mantissa
+ * m, out2[1] = log-scale s, value = m * exp(s).  After every site the
+ * environment is rescaled by a power of two (exact) and the exponent is
+ * summed in FP64.
+ * ------------------------------------------------------------------- */
+int32_t tn_mps_inner_workspace(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi,
+                               size_t* bytes);
+int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi, double* out2,
+                     void* workspace, size_t ws_bytes, int32_t prec, void* stream);
+
+/* Many independent inner products in one call (chains of uneven length and
+ * bond dimension).  psi_sites/phi_sites hold all chains' sites back to back;
+ * chain c owns sites [site_offsets[c], site_offsets[c+1]).  out2 is DEVICE,
+ * 2 doubles per chain.  Chains advance together, one site per step, as a
+ * grouped GEMM over all chains still active. */
+int32_t tn_mps_inner_batched_workspace(int32_t n_chains, const int32_t* site_offsets,
+                                       const tn_tensor* psi_sites, const tn_tensor* phi_sites,
+                                       size_t* bytes);
+int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets,
+                             const tn_tensor* psi_sites, const tn_tensor* phi_sites, double* out2,
+                             void* workspace, size_t ws_bytes, int32_t prec, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Operator environments of <psi|H|psi> for an MPO H.  psi[k]: TN_F32
+ * [D_k, d, D_{k+1}]; mpo[k]: TN_F32 [w_k, w_{k+1}, t, s] = <t|O|s> with
+ * w_0 = w_N = 1.
+ *   L_0 = 1, L_{k+1}[b', v, b] = sum A_k[a',t,b'] W_k[u,v,t,s] L_k[a',u,a] A_k[a,s,b]
+ *   R_N = 1, R_k[a', u, a]     = sum A_k[a',t,b'] W_k[u,v,t,s] R_{k+1}[b',v,b] A_k[a,s,b]
+ * L_out / R_out: arrays of N+1 TN_F32 tensors [D_k, w_k, D_k] (any strides),
+ * or NULL to skip that direction's stores (the sweep still runs when energy
+ * is requested).  energy2 (DEVICE, 2 doubles, nullable): [L_N, R_0].
+ * which: bit 0 = left sweep, bit 1 = right sweep.
+ * Each site is three steps: ket-site GEMM, MPO step, bra-site GEMM.
+ * ------------------------------------------------------------------- */
+int32_t tn_mps_env_sweep_workspace(int32_t n_sites, const tn_tensor* psi, const tn_tensor* mpo,
+                                   size_t* bytes);
+int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor* mpo,
+                         tn_tensor* L_out, tn_tensor* R_out, double* energy2, int32_t which,
+                         void* workspace, size_t ws_bytes, int32_t prec, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Left-canonical gauge in FP64 on the GPU (support step for the operator
+ * sweeps): A_k reshaped (D_k d, D_{k+1}) = Q R by Householder QR with
+ * diag(R) >= 0; Q replaces A_k, R is absorbed into A_{k+1}; the final 1x1 R
+ * is the state's norm, written as its logarithm to *lognorm (DEVICE) and
+ * divided out.  sites: TN_F64, contiguous, modified in place.  Requires
+ * D_{k+1} <= d * D_k.
+ * ------------------------------------------------------------------- */
+int32_t tn_mps_left_canonicalize_workspace(int32_t n_sites, const tn_tensor* sites, size_t* bytes);
+int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* lognorm,
+                                 void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * MPS classifier (section IV.A).  sites[k]: TN_F32 contiguous
+ * [D_k, 2, D_{k+1}] except sites[label_site] = [D_c, 2, n_labels, D_{c+1}];
+ * D_0 = D_N = 1 and all inner bonds equal (chi).  pixels: TN_F32 [B, N] in
+ * [0, 1], encoded by Phi(p) = (cos(pi p/2), sin(pi p/2)).
+ * logits: TN_F32 [B, n_labels], f[b, l] = <W^l, Phi(x_b)>.
+ * Forward keeps every left/right environment vector of each sample on chip
+ * and stores one of every `ckpt_every` of them to ckpt (nullable; FP32,
+ * layout documented by tn_mps_classifier_ckpt_shape) for the backward.
+ * Backward: dlogits [B, n_labels] -> dsites (same shapes as sites); it
+ * recomputes the vectors between checkpoints.  prec: FP32 or SPLIT_BF16.
+ * ------------------------------------------------------------------- */
+int32_t tn_mps_classifier_ckpt_shape(int32_t n_sites, int32_t label_site, int32_t batch,
+                                     int32_t chi, int32_t ckpt_every, int64_t* n_floats);
+int32_t tn_mps_classifier_workspace(int32_t n_sites, int32_t label_site, int32_t n_labels,
+                                    int32_t batch, int32_t chi, int32_t ckpt_every,
+                                    size_t* bytes);
+int32_t tn_mps_classifier_forward(int32_t n_sites, int32_t label_site, int32_t n_labels,
+                                  const tn_tensor* sites, const tn_tensor* pixels,
+                                  tn_tensor* logits, float* ckpt, int32_t ckpt_every,
+                                  void* workspace, size_t ws_bytes, int32_t prec, void* stream);
+int32_t tn_mps_classifier_backward(int32_t n_sites, int32_t label_site, int32_t n_labels,
+                                   const tn_tensor* sites, const tn_tensor* pixels,
+                                   const float* ckpt, int32_t ckpt_every,
+                                   const tn_tensor* dlogits, tn_tensor* dsites, void* workspace,
+                                   size_t ws_bytes, int32_t prec, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Tile autotuner for the contraction GEMM.  level 0: heuristic tiles only;
+ * 1: time the candidate tiles once per new (shape, layout, precision)
+ * signature on first use and cache the fastest.  The cache is process-wide
+ * and mutex-guarded.  tn_tune_lookup reports the tile id chosen for the
+ * last contraction on this thread (for logging).
+ * ------------------------------------------------------------------- */
+int32_t tn_tune_set_level(int32_t level);
+int32_t tn_tune_last_choice(void);
+/* Pin one tile configuration (0 .. tn_tune_num_configs()-1) for every
+ * subsequent contraction GEMM in the process; -1 restores automatic choice.
+ * Meant for measurement. */
+int32_t tn_tune_force_config(int32_t cfg);
+int32_t tn_tune_num_configs(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TN_H */

@@ -1,0 +1,25 @@
+"""MI355X (gfx950) tensor-network contraction library.
+
+Python entry points mirror the C ABI in include/tn.h; the arithmetic runs in
+libtn.so (hand-written HIP kernels).  Importing the package does not load
+the library; the first call does, and fails loudly if it is not built.
+"""
+from .api import (  # noqa: F401
+    BatchedInner,
+    EnvSweep,
+    contract_between,
+    contract_network,
+    mps_env_sweep,
+    mps_inner,
+    mps_inner_batched,
+    mps_left_canonicalize,
+    outer_product,
+    tensordot,
+    trace_edge,
+    tune_force_config,
+    tune_last_choice,
+    tune_num_configs,
+    tune_set_level,
+)
+
+__version__ = "0.1.0"

@@ -1,0 +1,208 @@
+"""Python entry points with the names of the C ABI (include/tn.h).
+
+Each function checks nothing beyond what ctypes needs, allocates outputs and
+workspaces with torch on the current device, and calls libtn.so on torch's
+current stream.  All arithmetic runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+def _dev(t):
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU (there is no CPU path)")
+    return t
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def contract_between(a, b, axes_a, axes_b, out=None, prec="fp32"):
+    """Contract axes_a[i] of a with axes_b[i] of b (section III.B, flattened edges).
+
+    Output axes: free axes of a (ascending) then free axes of b.  `out` may be
+    any strided view of that shape (a permuted view fuses reorder_edges).
+    """
+    _dev(a), _dev(b)
+    axes_a = [int(x) % max(a.dim(), 1) for x in axes_a]
+    axes_b = [int(x) % max(b.dim(), 1) for x in axes_b]
+    if out is None:
+        shape = [a.shape[i] for i in range(a.dim()) if i not in axes_a] + \
+                [b.shape[j] for j in range(b.dim()) if j not in axes_b]
+        out = torch.empty(shape, dtype=torch.float32, device=a.device)
+    da, db, do = L.tensor_desc(a), L.tensor_desc(b), L.tensor_desc(out)
+    L.check(L.lib().tn_contract_between(C.byref(da), C.byref(db), len(axes_a), L.int_array(axes_a),
+                                        L.int_array(axes_b), C.byref(do), L.prec_code(prec), L.stream_ptr()))
+    return out
+
+
+def tensordot(a, b, axes_a, axes_b, prec="fp32"):
+    return contract_between(a, b, axes_a, axes_b, prec=prec)
+
+
+def trace_edge(a, axis1, axis2, out=None):
+    """Trace over two axes of one node (section III.A, trace edges)."""
+    _dev(a)
+    a1, a2 = int(axis1) % a.dim(), int(axis2) % a.dim()
+    if out is None:
+        shape = [a.shape[i] for i in range(a.dim()) if i not in (a1, a2)]
+        out = torch.empty(shape, dtype=torch.float32, device=a.device)
+    da, do = L.tensor_desc(a), L.tensor_desc(out)
+    L.check(L.lib().tn_trace_edge(C.byref(da), a1, a2, C.byref(do), L.stream_ptr()))
+    return out
+
+
+def outer_product(a, b, out=None):
+    """(A (x) B)[i..., j...] = A[i...] B[j...] (section III.B)."""
+    _dev(a), _dev(b)
+    if out is None:
+        out = torch.empty(list(a.shape) + list(b.shape), dtype=torch.float32, device=a.device)
+    da, db, do = L.tensor_desc(a), L.tensor_desc(b), L.tensor_desc(out)
+    L.check(L.lib().tn_outer_product(C.byref(da), C.byref(db), C.byref(do), L.stream_ptr()))
+    return out
+
+
+def contract_network(tensors, labels, order=None, out=None, prec="fp32"):
+    """ncon (Appendix B): labels >= 0 connect, labels < 0 are outputs -1, -2, ..."""
+    for t in tensors:
+        _dev(t)
+    flat, offs = [], [0]
+    for l in labels:
+        flat.extend(int(x) for x in l)
+        offs.append(len(flat))
+    nodes = L.tensor_array(tensors)
+    lab = L.int_array(flat)
+    off = L.int_array(offs)
+    order = list(order) if order is not None else []
+    ordp = L.int_array(order)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_contract_network_workspace(len(tensors), nodes, lab, off, len(order), ordp, C.byref(nbytes)))
+    if out is None:
+        dims = {}
+        for t, l in zip(tensors, labels):
+            for ax, x in enumerate(l):
+                dims[int(x)] = t.shape[ax]
+        n_out = sum(1 for x in flat if x < 0)
+        out = torch.empty([dims[-(q + 1)] for q in range(n_out)], dtype=torch.float32, device=tensors[0].device)
+    ws = _workspace(nbytes.value, tensors[0].device)
+    do = L.tensor_desc(out)
+    L.check(L.lib().tn_contract_network(len(tensors), nodes, lab, off, len(order), ordp, C.byref(do),
+                                        C.c_void_p(ws.data_ptr()), nbytes.value, L.prec_code(prec), L.stream_ptr()))
+    return out
+
+
+def mps_inner(psi, phi, prec="fp32"):
+    """<psi|phi> as a device float64 tensor [m, s] with value m * exp(s)."""
+    n = len(psi)
+    dp, dq = L.tensor_array(psi), L.tensor_array(phi)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_mps_inner_workspace(n, dp, dq, C.byref(nbytes)))
+    dev = psi[0].device
+    ws = _workspace(nbytes.value, dev)
+    out2 = torch.empty(2, dtype=torch.float64, device=dev)
+    L.check(L.lib().tn_mps_inner(n, dp, dq, C.c_void_p(out2.data_ptr()), C.c_void_p(ws.data_ptr()), nbytes.value,
+                                 L.prec_code(prec), L.stream_ptr()))
+    return out2
+
+
+class BatchedInner:
+    """Prepared uneven batch: descriptors are built once, run() can be repeated."""
+
+    def __init__(self, chains, prec="fp32"):
+        self.psi = [t for p, _ in chains for t in p]
+        self.phi = [t for _, q in chains for t in q]
+        offs = [0]
+        for p, _ in chains:
+            offs.append(offs[-1] + len(p))
+        self.n = len(chains)
+        self.offs = L.int_array(offs)
+        self.dp, self.dq = L.tensor_array(self.psi), L.tensor_array(self.phi)
+        nbytes = C.c_size_t(0)
+        L.check(L.lib().tn_mps_inner_batched_workspace(self.n, self.offs, self.dp, self.dq, C.byref(nbytes)))
+        dev = self.psi[0].device
+        self.nbytes = nbytes.value
+        self.ws = _workspace(self.nbytes, dev)
+        self.out2 = torch.empty((self.n, 2), dtype=torch.float64, device=dev)
+        self.prec = L.prec_code(prec)
+
+    def run(self):
+        L.check(L.lib().tn_mps_inner_batched(self.n, self.offs, self.dp, self.dq, C.c_void_p(self.out2.data_ptr()),
+                                             C.c_void_p(self.ws.data_ptr()), self.nbytes, self.prec, L.stream_ptr()))
+        return self.out2
+
+
+def mps_inner_batched(chains, prec="fp32"):
+    """Inner products of many (psi, phi) chains of uneven length and bond dimension."""
+    return BatchedInner(chains, prec).run()
+
+
+class EnvSweep:
+    """Prepared MPS-MPO-MPS environment sweep (workspace and outputs allocated once)."""
+
+    def __init__(self, psi, mpo, left=True, right=True, store=True, prec="fp32"):
+        self.n = len(psi)
+        self.psi, self.mpo = psi, mpo
+        self.dp = L.tensor_array(psi)
+        self.dw = L.tensor_array(mpo)
+        nbytes = C.c_size_t(0)
+        L.check(L.lib().tn_mps_env_sweep_workspace(self.n, self.dp, self.dw, C.byref(nbytes)))
+        dev = psi[0].device
+        self.nbytes = nbytes.value
+        self.ws = _workspace(self.nbytes, dev)
+        dims = [1] + [int(a.shape[2]) for a in psi]
+        ws_ = [1] + [int(w.shape[1]) for w in mpo]
+        self.which = (1 if left else 0) | (2 if right else 0)
+        self.L = [torch.empty((dims[k], ws_[k], dims[k]), device=dev) for k in range(self.n + 1)] if (store and left) else None
+        self.R = [torch.empty((dims[k], ws_[k], dims[k]), device=dev) for k in range(self.n + 1)] if (store and right) else None
+        self.dL = L.tensor_array(self.L) if self.L else None
+        self.dR = L.tensor_array(self.R) if self.R else None
+        self.energy = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.prec = L.prec_code(prec)
+
+    def run(self):
+        L.check(L.lib().tn_mps_env_sweep(self.n, self.dp, self.dw, self.dL, self.dR, C.c_void_p(self.energy.data_ptr()),
+                                         self.which, C.c_void_p(self.ws.data_ptr()), self.nbytes, self.prec,
+                                         L.stream_ptr()))
+        return self
+
+
+def mps_env_sweep(psi, mpo, left=True, right=True, store=True, prec="fp32"):
+    """Left/right environments of <psi|H|psi>; returns (Ls, Rs, energy[L_N, R_0])."""
+    s = EnvSweep(psi, mpo, left, right, store, prec).run()
+    return s.L, s.R, s.energy
+
+
+def mps_left_canonicalize(sites):
+    """In-place FP64 left-canonical gauge (Householder QR); returns the log-norm (device)."""
+    n = len(sites)
+    ds = L.tensor_array(sites)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_mps_left_canonicalize_workspace(n, ds, C.byref(nbytes)))
+    dev = sites[0].device
+    ws = _workspace(nbytes.value, dev)
+    lognorm = torch.empty(1, dtype=torch.float64, device=dev)
+    L.check(L.lib().tn_mps_left_canonicalize(n, ds, C.c_void_p(lognorm.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                             nbytes.value, L.stream_ptr()))
+    return lognorm
+
+
+def tune_set_level(level: int):
+    L.check(L.lib().tn_tune_set_level(int(level)))
+
+
+def tune_force_config(cfg: int):
+    L.check(L.lib().tn_tune_force_config(int(cfg)))
+
+
+def tune_last_choice() -> int:
+    return int(L.lib().tn_tune_last_choice())
+
+
+def tune_num_configs() -> int:
+    return int(L.lib().tn_tune_num_configs())

@@ -1,0 +1,269 @@
+// Uneven batch of MPS inner products in one call.  All chains advance one
+// site per step; each step is two grouped GEMM launches (ket site into the
+// environment, then the bra site) over every chain still active, with the
+// problems of a launch described by a compact table in the workspace.  Within
+// a launch the problems are ordered by size, largest first, so the longest
+// tiles start earliest.  Problems are binned into three tile sizes.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace tn {
+
+static size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct ChainRec {
+  float* e[2];
+  uint32_t* slots;
+  int32_t n;
+  int32_t pad;
+};
+
+__global__ void batched_init_kernel(const ChainRec* chains, int n_chains) {
+  const int c = blockIdx.x;
+  if (c >= n_chains) return;
+  const ChainRec r = chains[c];
+  for (int i = threadIdx.x; i <= r.n; i += blockDim.x) r.slots[i] = i == 0 ? 0x3f800000u : 0u;
+  if (threadIdx.x == 0) r.e[0][0] = 1.0f;
+}
+
+__device__ inline int slot_exponent(uint32_t bits) {
+  int e = (int)((bits >> 23) & 0xffu);
+  if (e == 0 || e > 253) return 0;
+  return e - 127;
+}
+
+__global__ void batched_finish_kernel(const ChainRec* chains, int n_chains, double* out2) {
+  const int c = blockIdx.x;
+  if (c >= n_chains) return;
+  const ChainRec r = chains[c];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < r.n; i += 64) s += (double)slot_exponent(r.slots[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) {
+    out2[2 * c] = (double)r.e[r.n & 1][0];
+    out2[2 * c + 1] = s * 0.69314718055994530942;
+  }
+}
+
+namespace {
+
+struct Launch {
+  size_t prob_off;   // index into the problem table
+  int32_t n_probs;
+  size_t tile_off;   // index into the tile-start table
+  int32_t tiles;
+  int cfg;
+};
+
+struct BatchPlan {
+  std::vector<ChainRec> chains;
+  std::vector<Gemm2D> probs;
+  std::vector<int32_t> tstart;
+  std::vector<Launch> launches;
+  size_t chain_bytes = 0, chain_tab = 0, prob_tab = 0, tile_tab = 0, total = 0;
+};
+
+bool is_contiguous(const tn_tensor& t) {
+  int64_t st = 1;
+  for (int k = t.rank - 1; k >= 0; --k) {
+    if (t.shape[k] > 1 && t.stride[k] != st) return false;
+    st *= t.shape[k];
+  }
+  return true;
+}
+
+int bin_of(int64_t M, int64_t N) {
+  if (M <= 32 && N <= 32) return 2;
+  if (M * N >= 4ll * 128 * 128) return 0;
+  return 1;
+}
+
+int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const tn_tensor* phi, char* ws,
+              BatchPlan& P) {
+  if (n_chains < 1) return fail(TN_ERR_INVALID_ARGUMENT, "n_chains must be >= 1");
+  if (!off || !psi || !phi) return fail(TN_ERR_INVALID_ARGUMENT, "NULL chain description");
+  if (off[0] != 0) return fail(TN_ERR_INVALID_ARGUMENT, "site_offsets[0] must be 0");
+  std::vector<std::vector<int64_t>> dp(n_chains), dq(n_chains);
+  std::vector<int64_t> phys(n_chains);
+  std::vector<size_t> ebytes(n_chains), tbytes(n_chains);
+  size_t chain_total = 0;
+  int max_n = 0;
+  for (int c = 0; c < n_chains; ++c) {
+    const int n = off[c + 1] - off[c];
+    if (n < 1) return fail(TN_ERR_INVALID_ARGUMENT, "chain %d has no sites", c);
+    max_n = std::max(max_n, n);
+    for (int k = 0; k < n; ++k) {
+      const tn_tensor& a = psi[off[c] + k];
+      const tn_tensor& b = phi[off[c] + k];
+      TN_TRY(check_tensor(&a, "psi_sites[i]", TN_F32));
+      TN_TRY(check_tensor(&b, "phi_sites[i]", TN_F32));
+      if (a.rank != 3 || b.rank != 3) return fail(TN_ERR_SHAPE_MISMATCH, "chain %d site %d: sites must be rank 3", c, k);
+      if (!is_contiguous(a) || !is_contiguous(b))
+        return fail(TN_ERR_UNSUPPORTED, "chain %d site %d: batched sites must be contiguous", c, k);
+      if (k == 0) {
+        if (a.shape[0] != 1 || b.shape[0] != 1) return fail(TN_ERR_SHAPE_MISMATCH, "chain %d: first bond must be 1", c);
+        phys[c] = a.shape[1];
+        dp[c].push_back(1);
+        dq[c].push_back(1);
+      } else if (a.shape[0] != dp[c].back() || b.shape[0] != dq[c].back()) {
+        return fail(TN_ERR_SHAPE_MISMATCH, "chain %d: bond %d does not match", c, k);
+      }
+      if (a.shape[1] != phys[c] || b.shape[1] != phys[c])
+        return fail(TN_ERR_SHAPE_MISMATCH, "chain %d site %d: physical dimensions differ", c, k);
+      dp[c].push_back(a.shape[2]);
+      dq[c].push_back(b.shape[2]);
+    }
+    if (dp[c].back() != 1 || dq[c].back() != 1) return fail(TN_ERR_SHAPE_MISMATCH, "chain %d: last bond must be 1", c);
+    int64_t me = 1, mt = 1;
+    for (int k = 0; k <= n; ++k) me = std::max(me, dp[c][k] * dq[c][k]);
+    for (int k = 0; k < n; ++k) mt = std::max(mt, dp[c][k] * phys[c] * dq[c][k + 1]);
+    ebytes[c] = align256b(me * 4);
+    tbytes[c] = align256b(mt * 4);
+    chain_total += 2 * ebytes[c] + tbytes[c] + align256b((size_t)(n + 1) * 4);
+  }
+  // problem tables
+  std::vector<int> order(n_chains);
+  std::iota(order.begin(), order.end(), 0);
+  P.chains.resize(n_chains);
+  size_t o = 0;
+  std::vector<float*> tbuf(n_chains);
+  for (int c = 0; c < n_chains; ++c) {
+    ChainRec& r = P.chains[c];
+    r.e[0] = reinterpret_cast<float*>(ws + o);
+    o += ebytes[c];
+    r.e[1] = reinterpret_cast<float*>(ws + o);
+    o += ebytes[c];
+    tbuf[c] = reinterpret_cast<float*>(ws + o);
+    o += tbytes[c];
+    r.slots = reinterpret_cast<uint32_t*>(ws + o);
+    r.n = off[c + 1] - off[c];
+    r.pad = 0;
+    o += align256b((size_t)(r.n + 1) * 4);
+  }
+  P.chain_bytes = o;
+  for (int j = 0; j < max_n; ++j) {
+    for (int g = 0; g < 2; ++g) {
+      std::vector<std::pair<int64_t, Gemm2D>> bins[3];
+      for (int c = 0; c < n_chains; ++c) {
+        const int n = off[c + 1] - off[c];
+        if (j >= n) continue;
+        const tn_tensor& a = psi[off[c] + j];
+        const tn_tensor& b = phi[off[c] + j];
+        const int64_t pa = dp[c][j], qa = dq[c][j], d = phys[c], pb = dp[c][j + 1], qb = dq[c][j + 1];
+        ChainRec& r = P.chains[c];
+        Gemm2D q;
+        std::memset(&q, 0, sizeof(q));
+        if (g == 0) {  // T[a', (s b)] = sum_a E[a', a] phi[a, (s b)]
+          q.a = r.e[j & 1];
+          q.b = static_cast<const float*>(b.data);
+          q.c = tbuf[c];
+          q.M = (int32_t)pa;
+          q.K = (int32_t)qa;
+          q.N = (int32_t)(d * qb);
+          q.sam = qa;
+          q.sak = 1;
+          q.sbk = d * qb;
+          q.sbn = 1;
+          q.scm = d * qb;
+          q.scn = 1;
+          q.a_scale_bits = r.slots + j;
+        } else {  // E'[b', b] = sum_{(a' s)} psi[(a' s), b'] T[(a' s), b]
+          q.a = static_cast<const float*>(a.data);
+          q.b = tbuf[c];
+          q.c = r.e[(j + 1) & 1];
+          q.M = (int32_t)pb;
+          q.K = (int32_t)(pa * d);
+          q.N = (int32_t)qb;
+          q.sam = 1;
+          q.sak = pb;
+          q.sbk = qb;
+          q.sbn = 1;
+          q.scm = qb;
+          q.scn = 1;
+          q.c_absmax = r.slots + j + 1;
+        }
+        bins[bin_of(q.M, q.N)].push_back({(int64_t)q.M * q.N * q.K, q});
+      }
+      for (int bi = 0; bi < 3; ++bi) {
+        auto& v = bins[bi];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+        Launch L;
+        L.prob_off = P.probs.size();
+        L.n_probs = (int32_t)v.size();
+        L.tile_off = P.tstart.size();
+        L.cfg = bi;
+        const int tm = grouped_tile_m(bi), tn_ = grouped_tile_n(bi);
+        int64_t t = 0;
+        for (auto& e : v) {
+          P.tstart.push_back((int32_t)t);
+          t += (int64_t)((e.second.M + tm - 1) / tm) * ((e.second.N + tn_ - 1) / tn_);
+          P.probs.push_back(e.second);
+        }
+        if (t >= (1ll << 31)) return fail(TN_ERR_UNSUPPORTED, "too many tiles in one step");
+        L.tiles = (int32_t)t;
+        P.launches.push_back(L);
+      }
+    }
+  }
+  P.chain_tab = align256b(P.chain_bytes);
+  P.prob_tab = P.chain_tab + align256b(P.chains.size() * sizeof(ChainRec));
+  P.tile_tab = P.prob_tab + align256b(P.probs.size() * sizeof(Gemm2D));
+  P.total = P.tile_tab + align256b(P.tstart.size() * sizeof(int32_t));
+  return TN_OK;
+}
+
+}  // namespace
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+int32_t tn_mps_inner_batched_workspace(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
+                                       const tn_tensor* phi_sites, size_t* bytes) {
+  if (!bytes) return fail(TN_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  BatchPlan P;
+  TN_TRY(build(n_chains, site_offsets, psi_sites, phi_sites, nullptr, P));
+  *bytes = P.total;
+  return TN_OK;
+}
+
+int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
+                             const tn_tensor* phi_sites, double* out2, void* workspace, size_t ws_bytes, int32_t prec,
+                             void* stream) {
+  if (!out2) return fail(TN_ERR_INVALID_ARGUMENT, "out2 is NULL");
+  if (prec < 0 || prec > 3) return fail(TN_ERR_UNSUPPORTED, "unknown precision %d", prec);
+  BatchPlan P;
+  TN_TRY(build(n_chains, site_offsets, psi_sites, phi_sites, nullptr, P));
+  if (ws_bytes < P.total || !workspace) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", P.total);
+  BatchPlan Q;
+  char* ws = static_cast<char*>(workspace);
+  TN_TRY(build(n_chains, site_offsets, psi_sites, phi_sites, ws, Q));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ChainRec* d_chains = reinterpret_cast<ChainRec*>(ws + Q.chain_tab);
+  Gemm2D* d_probs = reinterpret_cast<Gemm2D*>(ws + Q.prob_tab);
+  int32_t* d_tiles = reinterpret_cast<int32_t*>(ws + Q.tile_tab);
+  TN_TRY(hip_check(hipMemcpyAsync(d_chains, Q.chains.data(), Q.chains.size() * sizeof(ChainRec), hipMemcpyHostToDevice, st),
+                   "chain table upload"));
+  TN_TRY(hip_check(hipMemcpyAsync(d_probs, Q.probs.data(), Q.probs.size() * sizeof(Gemm2D), hipMemcpyHostToDevice, st),
+                   "problem table upload"));
+  TN_TRY(hip_check(hipMemcpyAsync(d_tiles, Q.tstart.data(), Q.tstart.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+                   "tile table upload"));
+  // the host tables are released when this call returns
+  TN_TRY(hip_check(hipStreamSynchronize(st), "table upload"));
+  hipLaunchKernelGGL(batched_init_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains);
+  TN_TRY(hip_check(hipGetLastError(), "batched init"));
+  for (const Launch& L : Q.launches)
+    TN_TRY(launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off, L.n_probs, L.tiles, prec, L.cfg, st));
+  hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains, out2);
+  return hip_check(hipGetLastError(), "batched finish");
+}
+
+}  // extern "C"

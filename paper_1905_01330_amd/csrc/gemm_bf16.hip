@@ -1,0 +1,7 @@
+// Contraction GEMM instantiations for bf16 operands.
+#include "gemm_inst.h"
+
+namespace tn {
+GemmFn gemm_fn_bf16(int cfg) { return gemm_fn<P_BF16>(cfg); }
+GroupedFn grouped_fn_bf16(int cfg) { return grouped_fn<P_BF16>(cfg); }
+}  // namespace tn

@@ -1,0 +1,31 @@
+// Precision dispatch of the contraction GEMM instantiation tables.
+#include "gemm_inst_decl.h"
+
+namespace tn {
+GemmFn gemm_fn_fp32(int cfg);
+GemmFn gemm_fn_bf16(int cfg);
+GemmFn gemm_fn_x6(int cfg);
+GemmFn gemm_fn_x3(int cfg);
+GroupedFn grouped_fn_fp32(int cfg);
+GroupedFn grouped_fn_bf16(int cfg);
+GroupedFn grouped_fn_x6(int cfg);
+GroupedFn grouped_fn_x3(int cfg);
+
+GemmFn gemm_fn_prec(int prec, int cfg) {
+  switch (prec) {
+    case TN_PREC_FP32: return gemm_fn_fp32(cfg);
+    case TN_PREC_BF16: return gemm_fn_bf16(cfg);
+    case TN_PREC_SPLIT_BF16: return gemm_fn_x6(cfg);
+    default: return gemm_fn_x3(cfg);
+  }
+}
+
+GroupedFn grouped_fn_prec(int prec, int cfg) {
+  switch (prec) {
+    case TN_PREC_FP32: return grouped_fn_fp32(cfg);
+    case TN_PREC_BF16: return grouped_fn_bf16(cfg);
+    case TN_PREC_SPLIT_BF16: return grouped_fn_x6(cfg);
+    default: return grouped_fn_x3(cfg);
+  }
+}
+}  // namespace tn

@@ -1,0 +1,7 @@
+// Contraction GEMM instantiations for fp32 operands.
+#include "gemm_inst.h"
+
+namespace tn {
+GemmFn gemm_fn_fp32(int cfg) { return gemm_fn<P_FP32>(cfg); }
+GroupedFn grouped_fn_fp32(int cfg) { return grouped_fn<P_FP32>(cfg); }
+}  // namespace tn

@@ -1,0 +1,106 @@
+// Kernel instantiation tables for the contraction GEMM (one translation unit
+// per precision so the instantiations compile in parallel).
+#pragma once
+
+#include "gemm_inst_decl.h"
+#include "gemm_kernel.h"
+
+namespace tn {
+
+template <int P, int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(WM* WN * 64) gemm_kernel(const GemmDesc d) {
+  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN>::lds_bytes];
+  __shared__ Group gk;
+  copy_group(gk, d.gk);
+  __syncthreads();
+  GemmTile<P, BM, BN, BK, WM, WN>::run(d, gk, blockIdx.x, blockIdx.z, smem);
+}
+
+// Grouped launch: the workgroup finds its problem by binary search over the
+// per-problem first-tile table, then expands the compact 2-D description
+// into a full descriptor held in LDS.
+template <int P, int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(WM* WN * 64)
+    gemm_grouped_kernel(const Gemm2D* probs, const int32_t* tile_start, int32_t n_probs) {
+  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN>::lds_bytes];
+  __shared__ GemmDesc sd;
+  __shared__ int32_t s_prob;
+  const int bid = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = n_probs - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= bid)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    s_prob = lo;
+    const Gemm2D& p = probs[lo];
+    GemmDesc& d = sd;
+    d.a = p.a;
+    d.b = p.b;
+    d.c = p.c;
+    d.M = p.M;
+    d.N = p.N;
+    d.K = p.K;
+    d.batch = 1;
+    d.a_bs = d.b_bs = d.c_bs = 0;
+    d.a_scale_bits = p.a_scale_bits;
+    d.c_absmax = p.c_absmax;
+    d.tiles_m = (p.M + BM - 1) / BM;
+    d.tiles_n = (p.N + BN - 1) / BN;
+    auto one = [](Group& g, int64_t dim, int64_t s0, int64_t s1) {
+      g.n = 1;
+      g.dim[0] = (uint32_t)dim;
+      uint32_t shr = 0;
+      while (shr < 32 && (1ull << shr) < (uint64_t)dim) ++shr;
+      g.mul[0] = (uint32_t)((((1ull << 32) * ((1ull << shr) - (uint64_t)dim)) / (uint64_t)dim) + 1);
+      g.shr[0] = shr;
+      g.s[0][0] = s0;
+      g.s[1][0] = s1;
+      g.s[2][0] = 0;
+    };
+    one(d.gm, p.M, p.sam, p.scm);
+    one(d.gn, p.N, p.sbn, p.scn);
+    one(d.gk, p.K, p.sak, p.sbk);
+    auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+    d.a_mode = (p.sak == 1 && p.K % 4 == 0 && p.sam % 4 == 0 && al(p.a)) ? LOAD_KVEC
+             : (p.sam == 1 && p.M % 4 == 0 && p.sak % 4 == 0 && al(p.a)) ? LOAD_MNVEC
+                                                                          : LOAD_GENERIC;
+    d.b_mode = (p.sbk == 1 && p.K % 4 == 0 && p.sbn % 4 == 0 && al(p.b)) ? LOAD_KVEC
+             : (p.sbn == 1 && p.N % 4 == 0 && p.sbk % 4 == 0 && al(p.b)) ? LOAD_MNVEC
+                                                                          : LOAD_GENERIC;
+    d.c_mode = (p.scm == 1 && p.M % 4 == 0 && p.scn % 4 == 0 && al(p.c)) ? STORE_MVEC : STORE_SCALAR;
+  }
+  __syncthreads();
+  GemmTile<P, BM, BN, BK, WM, WN>::run(sd, sd.gk, bid - tile_start[s_prob], 0, smem);
+}
+
+
+template <int P>
+GemmFn gemm_fn(int cfg) {
+  switch (cfg) {
+    case 0: return gemm_kernel<P, 256, 128, 16, 2, 2>;
+    case 1: return gemm_kernel<P, 128, 256, 16, 2, 2>;
+    case 2: return gemm_kernel<P, 128, 128, 16, 2, 2>;
+    case 3: return gemm_kernel<P, 128, 128, 32, 2, 2>;
+    case 4: return gemm_kernel<P, 128, 64, 32, 2, 2>;
+    case 5: return gemm_kernel<P, 64, 128, 32, 2, 2>;
+    case 6: return gemm_kernel<P, 64, 64, 32, 2, 2>;
+    default: return gemm_kernel<P, 32, 32, 32, 1, 1>;
+  }
+}
+
+template <int P>
+GroupedFn grouped_fn(int cfg) {
+  switch (cfg) {
+    case 0: return gemm_grouped_kernel<P, 128, 128, 32, 2, 2>;
+    case 1: return gemm_grouped_kernel<P, 64, 64, 32, 2, 2>;
+    default: return gemm_grouped_kernel<P, 32, 32, 32, 1, 1>;
+  }
+}
+
+
+
+}  // namespace tn

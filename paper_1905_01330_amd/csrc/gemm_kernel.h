@@ -1,0 +1,484 @@
+// Tiled matrix-core contraction kernel for gfx950 (CDNA4).
+//
+// C[m, n] = sum_k A[m, k] B[k, n] where A, B and C are arbitrary strided
+// views (the M, N and K indices are groups of tensor axes).  The index
+// permutation of a tensordot happens inside the global -> LDS gather: each
+// thread reads a 1x4 (k-contiguous) or 4x4 (m/n-contiguous, transposed in
+// registers) micro-block and writes it to LDS in the layout the MFMA operand
+// reads want (8 consecutive k per lane).  No separate transpose pass exists.
+//
+// Precisions: FP32 operands on v_mfma_f32_32x32x2_f32; BF16 operands on
+// v_mfma_f32_32x32x16_bf16; the compensated split keeps 2 or 3 BF16 terms
+// per operand in separate LDS planes and issues 3 or 6 term products per
+// k-step into the same FP32 accumulator registers.
+#pragma once
+
+#include "common.h"
+
+namespace tn {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+enum Prec : int { P_FP32 = 0, P_BF16 = 1, P_X6 = 2, P_X3 = 3 };
+
+template <int P>
+struct PrecInfo {
+  static constexpr int planes = (P == P_X6) ? 3 : (P == P_X3 ? 2 : 1);
+  static constexpr bool bf = (P != P_FP32);
+  // term products (i, j), smallest first, all into one accumulator
+  static constexpr int nprod = (P == P_X6) ? 6 : (P == P_X3 ? 3 : 1);
+};
+
+__device__ constexpr int prod_a(int P, int q) {
+  // x6: (1,1) (0,2) (2,0) (0,1) (1,0) (0,0);  x3: (0,1) (1,0) (0,0)
+  return P == P_X6 ? (q == 0 ? 1 : q == 1 ? 0 : q == 2 ? 2 : q == 3 ? 0 : q == 4 ? 1 : 0)
+       : P == P_X3 ? (q == 0 ? 0 : q == 1 ? 1 : 0)
+                   : 0;
+}
+__device__ constexpr int prod_b(int P, int q) {
+  return P == P_X6 ? (q == 0 ? 1 : q == 1 ? 2 : q == 2 ? 0 : q == 3 ? 1 : q == 4 ? 0 : 0)
+       : P == P_X3 ? (q == 0 ? 1 : q == 1 ? 0 : 0)
+                   : 0;
+}
+
+// exact power-of-two rescale factor 2^-e for a max-abs bit pattern (1 if unusable)
+__device__ inline float pow2_inverse_scale(uint32_t bits) {
+  uint32_t e = (bits >> 23) & 0xffu;
+  if (e == 0u || e > 253u) return 1.0f;
+  return __uint_as_float((254u - e) << 23);
+}
+
+template <int P, int R, int BK>
+struct LdsOperand {
+  static constexpr int LDK = BK + 4;   // fp32 row pitch (floats)
+  static constexpr int LDH = BK + 8;   // bf16 row pitch (elements)
+  static constexpr int bytes = PrecInfo<P>::bf ? R * LDH * 2 * PrecInfo<P>::planes : R * LDK * 4;
+};
+
+template <int P, int R, int BK>
+__device__ inline void lds_put4(char* base, int row, int kcol, f32x4_t v) {
+  if constexpr (!PrecInfo<P>::bf) {
+    float* p = reinterpret_cast<float*>(base);
+    *reinterpret_cast<f32x4_t*>(p + row * LdsOperand<P, R, BK>::LDK + kcol) = v;
+  } else {
+    constexpr int LDH = LdsOperand<P, R, BK>::LDH;
+    constexpr int plane = R * LDH;
+    __bf16* h = reinterpret_cast<__bf16*>(base) + row * LDH + kcol;
+    bf16x4_t t0, t1, t2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float x = v[q];
+      __bf16 x0 = (__bf16)x;
+      t0[q] = x0;
+      if constexpr (PrecInfo<P>::planes >= 2) {
+        float r1 = x - (float)x0;
+        __bf16 x1 = (__bf16)r1;
+        t1[q] = x1;
+        if constexpr (PrecInfo<P>::planes >= 3) {
+          float r2 = r1 - (float)x1;
+          t2[q] = (__bf16)r2;
+        }
+      }
+    }
+    *reinterpret_cast<bf16x4_t*>(h) = t0;
+    if constexpr (PrecInfo<P>::planes >= 2) *reinterpret_cast<bf16x4_t*>(h + plane) = t1;
+    if constexpr (PrecInfo<P>::planes >= 3) *reinterpret_cast<bf16x4_t*>(h + 2 * plane) = t2;
+  }
+}
+
+// Per-thread gather of one operand tile (R rows x BK k) per stage.
+//   which = 0: operand A (rows = M, strides gm.s[0], gk.s[0])
+//   which = 1: operand B (rows = N, strides gn.s[0], gk.s[1])
+template <int P, int R, int BK, int NT, int KIDX>
+struct OperandLoader {
+  static constexpr int KQ = BK / 4;
+  static constexpr int NKV = R * BK / 4;
+  static constexpr int NMV = R * BK / 16;
+  static constexpr int VK = (NKV + NT - 1) / NT;
+  static constexpr int VM = (NMV + NT - 1) / NT;
+  static constexpr int NREG = (VK > 4 * VM) ? VK : 4 * VM;
+  static constexpr int NROW = (VK > VM) ? VK : VM;
+
+  f32x4_t st[NREG];
+  int64_t rowoff[NROW];
+  uint32_t rowok;
+  int mode;
+  const float* base;
+  int K;
+  float scale;
+
+  // offset of contracted index k: one multiply for a single merged axis, else
+  // a short (not unrolled) digit loop, so the callers' loops stay unrollable
+  __device__ static inline int64_t koff(const Group& gk, int k) {
+    if (gk.n == 1) return (int64_t)k * gk.s[KIDX][0];
+    int64_t o = 0;
+    uint32_t idx = (uint32_t)k;
+#pragma unroll 1
+    for (int i = gk.n - 1; i >= 0; --i) {
+      uint32_t q = fast_div(idx, gk.mul[i], gk.shr[i]);
+      o += (int64_t)(idx - q * gk.dim[i]) * gk.s[KIDX][i];
+      idx = q;
+    }
+    return o;
+  }
+
+  __device__ __forceinline__ void init(int mode_, const float* base_, const Group& grows, int row0, int nrows, int K_,
+                              float scale_) {
+    mode = mode_;
+    base = base_;
+    K = K_;
+    scale = scale_;
+    rowok = 0;
+    const int tid = threadIdx.x;
+    if (mode != LOAD_MNVEC) {
+#pragma unroll
+      for (int v = 0; v < VK; ++v) {
+        int idx = tid + v * NT;
+        int row = row0 + idx / KQ;
+        rowoff[v] = 0;
+        if (idx < NKV && row < nrows) {
+          int64_t o[1];
+          group_offsets<1>(grows, (uint32_t)row, o, 0);
+          rowoff[v] = o[0];
+          rowok |= 1u << v;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < VM; ++v) {
+        int idx = tid + v * NT;
+        int row = row0 + (idx % (R / 4)) * 4;
+        rowoff[v] = 0;
+        if (idx < NMV && row < nrows) {
+          int64_t o[1];
+          group_offsets<1>(grows, (uint32_t)row, o, 0);
+          rowoff[v] = o[0];
+          rowok |= 1u << v;
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void load(int k0, const Group& gk) {
+    const int tid = threadIdx.x;
+    if (mode == LOAD_KVEC) {
+#pragma unroll
+      for (int v = 0; v < VK; ++v) {
+        int idx = tid + v * NT;
+        int k = k0 + (idx % KQ) * 4;
+        f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+        if (((rowok >> v) & 1u) && k < K) x = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k));
+        st[v] = x;
+      }
+    } else if (mode == LOAD_GENERIC) {
+#pragma unroll
+      for (int v = 0; v < VK; ++v) {
+        int idx = tid + v * NT;
+        int k = k0 + (idx % KQ) * 4;
+        f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+        if ((rowok >> v) & 1u) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (k + j < K) x[j] = base[rowoff[v] + koff(gk, k + j)];
+        }
+        st[v] = x;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < VM; ++v) {
+        int idx = tid + v * NT;
+        int k = k0 + (idx / (R / 4)) * 4;
+        // the four k of the micro-block: one offset and the innermost stride
+        // when they share the innermost K run, else one offset each
+        const int last = gk.n - 1;
+        const int64_t ko = k < K ? koff(gk, k) : 0;
+        const bool run = gk.n == 1 || (k % (int)gk.dim[last]) + 3 < (int)gk.dim[last];
+        const int64_t ks = gk.s[KIDX][last];
+        const bool ok = (rowok >> v) & 1u;
+        f32x4_t x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0, x2 = x0, x3 = x0;
+        if (run) {
+          const float* p = base + rowoff[v] + ko;
+          if (ok && k + 0 < K) x0 = *reinterpret_cast<const f32x4_t*>(p);
+          if (ok && k + 1 < K) x1 = *reinterpret_cast<const f32x4_t*>(p + ks);
+          if (ok && k + 2 < K) x2 = *reinterpret_cast<const f32x4_t*>(p + 2 * ks);
+          if (ok && k + 3 < K) x3 = *reinterpret_cast<const f32x4_t*>(p + 3 * ks);
+        } else {
+          if (ok && k + 0 < K) x0 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 0));
+          if (ok && k + 1 < K) x1 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 1));
+          if (ok && k + 2 < K) x2 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 2));
+          if (ok && k + 3 < K) x3 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 3));
+        }
+        st[4 * v + 0] = x0;
+        st[4 * v + 1] = x1;
+        st[4 * v + 2] = x2;
+        st[4 * v + 3] = x3;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(char* lds) {
+    const int tid = threadIdx.x;
+    if (mode != LOAD_MNVEC) {
+#pragma unroll
+      for (int v = 0; v < VK; ++v) {
+        int idx = tid + v * NT;
+        if (idx < NKV) lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[v] * scale);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < VM; ++v) {
+        int idx = tid + v * NT;
+        if (idx < NMV) {
+          int r0 = (idx % (R / 4)) * 4;
+          int kc = (idx / (R / 4)) * 4;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            f32x4_t t = {st[4 * v + 0][i], st[4 * v + 1][i], st[4 * v + 2][i], st[4 * v + 3][i]};
+            lds_put4<P, R, BK>(lds, r0 + i, kc, t * scale);
+          }
+        }
+      }
+    }
+  }
+};
+
+// Copy an index group with static field accesses only (so a by-value kernel
+// argument is never indexed dynamically, which would force a private copy).
+__device__ __forceinline__ void copy_group(Group& dst, const Group& src) {
+  if (threadIdx.x == 0) {
+    dst.n = src.n;
+#pragma unroll
+    for (int i = 0; i < kMaxAxes; ++i) {
+      dst.dim[i] = src.dim[i];
+      dst.mul[i] = src.mul[i];
+      dst.shr[i] = src.shr[i];
+      dst.s[0][i] = src.s[0][i];
+      dst.s[1][i] = src.s[1][i];
+      dst.s[2][i] = src.s[2][i];
+    }
+  }
+}
+
+// XCD-aware tile order: the hardware deals workgroups round-robin over the 8
+// XCDs, so consecutive ids are remapped to one XCD's contiguous range, then
+// grouped by GROUP_M tile rows so neighbouring tiles share A rows and B
+// columns in that XCD's L2.
+__device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int T = tiles_m * tiles_n;
+  int local = bid;
+  if (T >= 16) {
+    const int x = bid & 7, i = bid >> 3;
+    const int q = T >> 3, r = T & 7;
+    local = x * q + (x < r ? x : r) + i;
+  }
+  constexpr int GROUP_M = 8;
+  const int per_group = GROUP_M * tiles_n;
+  const int g = local / per_group;
+  const int first_m = g * GROUP_M;
+  const int gsize = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
+  const int in_g = local - g * per_group;
+  tm = first_m + in_g % gsize;
+  tn = in_g / gsize;
+}
+
+template <int P, int BM, int BN, int BK, int WM, int WN>
+struct GemmTile {
+  static constexpr int NT = WM * WN * 64;
+  static constexpr int TM = BM / WM / 32;
+  static constexpr int TN = BN / WN / 32;
+  static constexpr int bytesA = LdsOperand<P, BM, BK>::bytes;
+  static constexpr int bytesB = LdsOperand<P, BN, BK>::bytes;
+  static constexpr int stage = bytesA + bytesB;
+  static constexpr int lds_bytes = 2 * stage;
+  static_assert(TM >= 1 && TN >= 1, "tile too small for 32x32 blocks");
+  static_assert(BK % 16 == 0, "BK must be a multiple of 16");
+
+  __device__ static __forceinline__ void compute(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN], int wm_off,
+                                        int wn_off) {
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 31, lh = lane >> 5;
+    if constexpr (!PrecInfo<P>::bf) {
+      constexpr int LDA = LdsOperand<P, BM, BK>::LDK;
+      constexpr int LDB = LdsOperand<P, BN, BK>::LDK;
+      const float* A = reinterpret_cast<const float*>(sa);
+      const float* B = reinterpret_cast<const float*>(sb);
+#pragma unroll
+      for (int kc = 0; kc < BK / 8; ++kc) {
+        f32x4_t af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          af[i] = *reinterpret_cast<const f32x4_t*>(A + (wm_off + 32 * i + lr) * LDA + kc * 8 + lh * 4);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          bfr[j] = *reinterpret_cast<const f32x4_t*>(B + (wn_off + 32 * j + lr) * LDB + kc * 8 + lh * 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], bfr[j][q], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      constexpr int LDA = LdsOperand<P, BM, BK>::LDH;
+      constexpr int LDB = LdsOperand<P, BN, BK>::LDH;
+      constexpr int NPL = PrecInfo<P>::planes;
+      const __bf16* A = reinterpret_cast<const __bf16*>(sa);
+      const __bf16* B = reinterpret_cast<const __bf16*>(sb);
+      constexpr int NKC = BK / 16;
+      bf16x8_t af[NKC][NPL][TM], bfr[NKC][NPL][TN];
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+            af[kc][p][i] = *reinterpret_cast<const bf16x8_t*>(A + p * BM * LDA + (wm_off + 32 * i + lr) * LDA + kc * 16 + lh * 8);
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            bfr[kc][p][j] = *reinterpret_cast<const bf16x8_t*>(B + p * BN * LDB + (wn_off + 32 * j + lr) * LDB + kc * 16 + lh * 8);
+        }
+      if constexpr (P == P_BF16) {
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][0][i], bfr[kc][0][j], acc[i][j], 0, 0, 0);
+      } else {
+        // The term products of this stage are summed by the matrix cores into a
+        // zero-based temporary, which is then added to the running accumulator
+        // with a round-to-nearest-even VALU add.  Repeated matrix-core
+        // accumulation onto a large running sum drifts (measured bias of about
+        // -1e-6 relative at K = 2048); a small temporary keeps that drift
+        // proportional to the temporary, not to the result.
+        const f32x16_t zero = {};
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          f32x16_t tmp[TM];
+#pragma unroll
+          for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+            for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+#pragma unroll
+              for (int i = 0; i < TM; ++i)
+                tmp[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][prod_a(P, q)][i], bfr[kc][prod_b(P, q)][j],
+                                                                 (kc == 0 && q == 0) ? zero : tmp[i], 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < TM; ++i) acc[i][j] += tmp[i];
+        }
+      }
+    }
+  }
+
+  // gk_lds: a copy of d.gk in LDS (the per-stage offset loop indexes it dynamically)
+  __device__ static __forceinline__ void run(const GemmDesc& d, const Group& gk_lds, int bid, int bz, char* smem) {
+    int tm, tn;
+    tile_coords(bid, d.tiles_m, d.tiles_n, tm, tn);
+    const int wave = threadIdx.x >> 6;
+    const int wm_off = (wave % WM) * (BM / WM);
+    const int wn_off = (wave / WM) * (BN / WN);
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    float scale = 1.0f;
+    if (d.a_scale_bits) scale = pow2_inverse_scale(d.a_scale_bits[bz]);
+
+    OperandLoader<P, BM, BK, NT, 0> la;
+    OperandLoader<P, BN, BK, NT, 1> lb;
+    la.init(d.a_mode, d.a + bz * d.a_bs, d.gm, m0, d.M, d.K, scale);
+    lb.init(d.b_mode, d.b + bz * d.b_bs, d.gn, n0, d.N, d.K, 1.0f);
+
+    f32x16_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int nk = (d.K + BK - 1) / BK;
+    la.load(0, gk_lds);
+    lb.load(0, gk_lds);
+    la.store(smem);
+    lb.store(smem + bytesA);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      char* cur = smem + (kt & 1) * stage;
+      char* nxt = smem + ((kt + 1) & 1) * stage;
+      const bool more = kt + 1 < nk;
+      if (more) {
+        la.load((kt + 1) * BK, gk_lds);
+        lb.load((kt + 1) * BK, gk_lds);
+      }
+      compute(cur, cur + bytesA, acc, wm_off, wn_off);
+      if (more) {
+        la.store(nxt);
+        lb.store(nxt + bytesA);
+      }
+      __syncthreads();
+    }
+
+    // epilogue.  The output offsets of the tile's BM rows and BN columns are
+    // formed once into LDS (free after the last stage), so the store loop is
+    // a short fully-unrolled sequence.  C layout of a 32x32 block: lane l,
+    // register r holds row 8*(r/4) + 4*(l/32) + r%4, column l%32.
+    static_assert((BM + BN) * 8 <= lds_bytes, "LDS too small for the offset tables");
+    int64_t* offm = reinterpret_cast<int64_t*>(smem);
+    int64_t* offn = offm + BM;
+    for (int e = threadIdx.x; e < BM + BN; e += NT) {
+      int64_t o[1] = {0};
+      if (e < BM) {
+        if (m0 + e < d.M) group_offsets<1>(d.gm, (uint32_t)(m0 + e), o, 1);
+        offm[e] = o[0];
+      } else {
+        if (n0 + e - BM < d.N) group_offsets<1>(d.gn, (uint32_t)(n0 + e - BM), o, 1);
+        offn[e - BM] = o[0];
+      }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 31, lh = lane >> 5;
+    float* C = d.c + bz * d.c_bs;
+    float amax = 0.f;
+    const bool mvec = d.c_mode == STORE_MVEC;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int nl = wn_off + 32 * j + lr;
+      const bool nok = n0 + nl < d.N;
+      const int64_t on = offn[nl];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ml = wm_off + 32 * i + 8 * q + 4 * lh;
+          const f32x4_t v = {acc[i][j][4 * q + 0], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+          if (nok && m0 + ml < d.M) {
+            if (mvec) {
+              *reinterpret_cast<f32x4_t*>(C + offm[ml] + on) = v;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) amax = fmaxf(amax, fabsf(v[r]));
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (m0 + ml + r < d.M) {
+                  C[offm[ml + r] + on] = v[r];
+                  amax = fmaxf(amax, fabsf(v[r]));
+                }
+            }
+          }
+        }
+      }
+    }
+    if (d.c_absmax) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+      if (lane == 0) atomicMax(d.c_absmax + bz, __float_as_uint(amax));
+    }
+  }
+};
+
+}  // namespace tn

@@ -1,0 +1,7 @@
+// Contraction GEMM instantiations for x6 operands.
+#include "gemm_inst.h"
+
+namespace tn {
+GemmFn gemm_fn_x6(int cfg) { return gemm_fn<P_X6>(cfg); }
+GroupedFn grouped_fn_x6(int cfg) { return grouped_fn<P_X6>(cfg); }
+}  // namespace tn

@@ -1,0 +1,62 @@
+// Host-side internal interfaces of the library.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace tn {
+
+// ---- tensors -------------------------------------------------------------
+int32_t check_tensor(const tn_tensor* t, const char* name, int32_t dtype);
+int64_t numel(const tn_tensor& t);
+// [lo, hi) byte range touched by a view (hi = lo for an empty view)
+void byte_extent(const tn_tensor& t, uintptr_t& lo, uintptr_t& hi);
+bool overlaps(const tn_tensor& a, const tn_tensor& b);
+bool has_internal_overlap(const tn_tensor& t);
+tn_tensor make_view(void* data, int32_t dtype, std::initializer_list<int64_t> shape);
+tn_tensor contiguous_view(void* data, int32_t dtype, int32_t rank, const int64_t* shape);
+
+// ---- GEMM plan (contraction of strided views) ------------------------------
+// Builds the GEMM view of a tensordot: M = free axes of a (ascending),
+// N = free axes of b (ascending), K = pairs in the given order.  Axes of
+// extent 1 are dropped and axes contiguous in every tensor of their group
+// are merged; each group is ordered so its most contiguous axis is inner.
+int32_t plan_gemm(const tn_tensor& a, const tn_tensor& b, int32_t n_pairs, const int32_t* axes_a,
+                  const int32_t* axes_b, const tn_tensor& out, GemmDesc& d);
+
+// reductions: out[r] = sum_k x * y (y may be null)
+struct AxisSpec {
+  int64_t dim;
+  int64_t s[3];
+};
+void build_group(std::vector<AxisSpec> axes, int primary, int n_strides, Group& g);
+int32_t launch_reduce(ReduceDesc& d, hipStream_t st);
+int32_t reduce_from_axes(const float* x, const float* y, float* out, const std::vector<AxisSpec>& r_axes,
+                         const std::vector<AxisSpec>& k_axes, bool bf16_round, hipStream_t st);
+
+// ---- GEMM launch -----------------------------------------------------------
+int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st);
+int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st);
+int gemm_num_cfgs();
+
+// grouped GEMM over compact 2-D problems (uneven batches)
+struct Gemm2D {
+  const float* a;
+  const float* b;
+  float* c;
+  int32_t M, N, K;
+  int64_t sam, sak, sbk, sbn, scm, scn;
+  const uint32_t* a_scale_bits;
+  uint32_t* c_absmax;
+};
+int32_t launch_gemm_grouped(const Gemm2D* dev_probs, const int32_t* dev_tile_start, int32_t n_probs,
+                            int32_t total_tiles, int32_t prec, int cfg, hipStream_t st);
+int grouped_tile_m(int cfg);
+int grouped_tile_n(int cfg);
+
+// ---- contraction entry used by the network driver -----------------------------
+int32_t contract_between_impl(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs, const int32_t* axes_a,
+                              const int32_t* axes_b, tn_tensor* out, int32_t prec, hipStream_t st);
+
+}  // namespace tn

@@ -1,0 +1,388 @@
+// Chain networks of Fig. 3a: MPS inner products (single and uneven batches)
+// and MPS-MPO-MPS environment sweeps.  Every site is a short sequence of
+// contraction GEMMs on the caller's stream; the inner product keeps its
+// running environment in range with exact power-of-two rescaling fused into
+// the GEMMs (the epilogue records max|E| with an atomic max, the next site's
+// operand gather multiplies by 2^-e) and sums the exponents in FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace tn {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// exponent e of a max-abs bit pattern such that the GEMM scaled by 2^-e (0 if unusable)
+__device__ inline int scale_exponent(uint32_t bits) {
+  int e = (int)((bits >> 23) & 0xffu);
+  if (e == 0 || e > 253) return 0;
+  return e - 127;
+}
+
+__global__ void mps_init_kernel(float* e0, uint32_t* slots, int n_slots) {
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_slots; i += blockDim.x * gridDim.x)
+    slots[i] = i == 0 ? 0x3f800000u : 0u;
+  if (threadIdx.x == 0 && blockIdx.x == 0) e0[0] = 1.0f;
+}
+
+__global__ void mps_finish_kernel(const float* e_final, const uint32_t* slots, int n_used, double* out2) {
+  __shared__ double part[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n_used; i += blockDim.x) s += (double)scale_exponent(slots[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = part[0] + part[1] + part[2] + part[3];
+    out2[0] = (double)e_final[0];
+    out2[1] = t * 0.69314718055994530942;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+
+static int32_t check_chain(int32_t n_sites, const tn_tensor* sites, const char* name, int32_t dtype,
+                           std::vector<int64_t>* dims, int64_t* phys) {
+  if (n_sites < 1) return fail(TN_ERR_INVALID_ARGUMENT, "n_sites must be >= 1");
+  if (!sites) return fail(TN_ERR_INVALID_ARGUMENT, "%s is NULL", name);
+  dims->clear();
+  for (int k = 0; k < n_sites; ++k) {
+    char nm[48];
+    snprintf(nm, sizeof(nm), "%s[%d]", name, k);
+    TN_TRY(check_tensor(&sites[k], nm, dtype));
+    if (sites[k].rank != 3) return fail(TN_ERR_SHAPE_MISMATCH, "%s must be [D_k, d, D_k+1]", nm);
+    if (k == 0) {
+      if (sites[0].shape[0] != 1) return fail(TN_ERR_SHAPE_MISMATCH, "%s: first bond must be 1", name);
+      *phys = sites[0].shape[1];
+      dims->push_back(1);
+    } else {
+      if (sites[k].shape[0] != dims->back()) return fail(TN_ERR_SHAPE_MISMATCH, "%s: bond %d does not match", name, k);
+    }
+    if (sites[k].shape[1] != *phys) return fail(TN_ERR_SHAPE_MISMATCH, "%s: physical dimension differs", nm);
+    dims->push_back(sites[k].shape[2]);
+  }
+  if (dims->back() != 1) return fail(TN_ERR_SHAPE_MISMATCH, "%s: last bond must be 1", name);
+  return TN_OK;
+}
+
+// GEMM views of one inner-product site (shared by the single and batched paths)
+//   T[a', s, b] = sum_a E[a', a] phi[a, s, b]        (E scaled by 2^-e of slot k)
+//   E'[b', b]  = sum_{a', s} psi[a', s, b'] T[a', s, b]
+static int32_t inner_site(const tn_tensor& psi, const tn_tensor& phi, float* e_in, float* e_out, float* t,
+                          uint32_t* slots, int k, int32_t prec, hipStream_t st) {
+  const int64_t da = psi.shape[0], db = phi.shape[0], d = psi.shape[1];
+  const int64_t da2 = psi.shape[2], db2 = phi.shape[2];
+  tn_tensor e = make_view(e_in, TN_F32, {da, db});
+  tn_tensor tv = make_view(t, TN_F32, {da, d, db2});
+  tn_tensor eo = make_view(e_out, TN_F32, {da2, db2});
+  const int32_t a1[1] = {1}, b1[1] = {0};
+  GemmDesc g;
+  TN_TRY(plan_gemm(e, phi, 1, a1, b1, tv, g));
+  g.a_scale_bits = slots + k;
+  TN_TRY(launch_gemm(g, prec, st));
+  const int32_t a2[2] = {0, 1}, b2[2] = {0, 1};
+  TN_TRY(plan_gemm(psi, tv, 2, a2, b2, eo, g));
+  g.c_absmax = slots + k + 1;
+  return launch_gemm(g, prec, st);
+}
+
+struct InnerLayout {
+  size_t e0, e1, t, slots, total;
+};
+
+static InnerLayout inner_layout(int32_t n, const std::vector<int64_t>& dp, const std::vector<int64_t>& dq, int64_t d) {
+  int64_t me = 1, mt = 1;
+  for (int k = 0; k <= n; ++k) me = std::max(me, dp[k] * dq[k]);
+  for (int k = 0; k < n; ++k) mt = std::max(mt, dp[k] * d * dq[k + 1]);
+  InnerLayout L;
+  L.e0 = 0;
+  L.e1 = align256(me * 4);
+  L.t = L.e1 + align256(me * 4);
+  L.slots = L.t + align256(mt * 4);
+  L.total = L.slots + align256((size_t)(n + 1) * 4);
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// MPO step kernels (contract the operator site with the T1 intermediate)
+
+constexpr int kMaxW = 8;
+constexpr int kMaxD = 4;
+
+// left:  T2[a', t, v, b] = sum_{u, s} W[u, v, t, s] T1[a', u, s, b]
+__global__ void __launch_bounds__(256) wstep_left_kernel(const float* __restrict__ t1, float* __restrict__ t2,
+                                                         const float* __restrict__ w, int64_t w0, int64_t w1, int64_t w2,
+                                                         int64_t w3, int da, int db, int wl, int wr, int d) {
+  __shared__ float sw[kMaxW * kMaxW * kMaxD * kMaxD];
+  const int nw = wl * wr * d * d;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    int s = i % d, t = (i / d) % d, v = (i / (d * d)) % wr, u = i / (d * d * wr);
+    sw[i] = w[u * w0 + v * w1 + t * w2 + s * w3];
+  }
+  __syncthreads();
+  const int64_t total = (int64_t)da * db;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = idx / db, b = idx - a * db;
+    float x[kMaxW * kMaxD];
+    for (int u = 0; u < wl; ++u)
+      for (int s = 0; s < d; ++s) x[u * kMaxD + s] = t1[((a * wl + u) * d + s) * db + b];
+    for (int t = 0; t < d; ++t)
+      for (int v = 0; v < wr; ++v) {
+        double acc = 0.0;
+        for (int u = 0; u < wl; ++u)
+          for (int s = 0; s < d; ++s) acc += (double)sw[((u * wr + v) * d + t) * d + s] * (double)x[u * kMaxD + s];
+        t2[((a * d + t) * wr + v) * db + b] = (float)acc;
+      }
+  }
+}
+
+// right: T2'[u, a, t, b'] = sum_{s, v} W[u, v, t, s] T1'[a, s, b', v]
+__global__ void __launch_bounds__(256) wstep_right_kernel(const float* __restrict__ t1, float* __restrict__ t2,
+                                                          const float* __restrict__ w, int64_t w0, int64_t w1, int64_t w2,
+                                                          int64_t w3, int da, int db, int wl, int wr, int d) {
+  __shared__ float sw[kMaxW * kMaxW * kMaxD * kMaxD];
+  const int nw = wl * wr * d * d;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    int s = i % d, t = (i / d) % d, v = (i / (d * d)) % wr, u = i / (d * d * wr);
+    sw[i] = w[u * w0 + v * w1 + t * w2 + s * w3];
+  }
+  __syncthreads();
+  const int64_t total = (int64_t)da * db;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = idx / db, b = idx - a * db;
+    float x[kMaxD * kMaxW];
+    for (int s = 0; s < d; ++s)
+      for (int v = 0; v < wr; ++v) x[s * kMaxW + v] = t1[((a * d + s) * db + b) * wr + v];
+    for (int u = 0; u < wl; ++u)
+      for (int t = 0; t < d; ++t) {
+        double acc = 0.0;
+        for (int s = 0; s < d; ++s)
+          for (int v = 0; v < wr; ++v) acc += (double)sw[((u * wr + v) * d + t) * d + s] * (double)x[s * kMaxW + v];
+        t2[((u * (int64_t)da + a) * d + t) * db + b] = (float)acc;
+      }
+  }
+}
+
+__global__ void fill_one_kernel(float* p) { p[0] = 1.0f; }
+
+__global__ void energy_kernel(const float* l_last, const float* r_first, double* e2) {
+  if (threadIdx.x == 0) {
+    e2[0] = l_last ? (double)l_last[0] : 0.0;
+    e2[1] = r_first ? (double)r_first[0] : 0.0;
+  }
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+struct EnvLayout {
+  size_t t1, t2, lbuf0, lbuf1, rbuf0, rbuf1, total;
+};
+
+static EnvLayout env_layout(int32_t n, const std::vector<int64_t>& dims, const std::vector<int64_t>& w, int64_t d) {
+  int64_t mt = 1, me = 1;
+  for (int k = 0; k < n; ++k) {
+    mt = std::max(mt, dims[k] * w[k] * d * dims[k + 1]);      // T1 left, T2' right
+    mt = std::max(mt, dims[k] * d * w[k + 1] * dims[k + 1]);  // T2 left, T1' right
+  }
+  for (int k = 0; k <= n; ++k) me = std::max(me, dims[k] * w[k] * dims[k]);
+  EnvLayout L;
+  L.t1 = 0;
+  L.t2 = align256(mt * 4);
+  L.lbuf0 = L.t2 + align256(mt * 4);
+  L.lbuf1 = L.lbuf0 + align256(me * 4);
+  L.rbuf0 = L.lbuf1 + align256(me * 4);
+  L.rbuf1 = L.rbuf0 + align256(me * 4);
+  L.total = L.rbuf1 + align256(me * 4);
+  return L;
+}
+
+static int32_t check_mpo(int32_t n, const tn_tensor* mpo, int64_t d, std::vector<int64_t>& w) {
+  if (!mpo) return fail(TN_ERR_INVALID_ARGUMENT, "mpo is NULL");
+  w.clear();
+  for (int k = 0; k < n; ++k) {
+    char nm[32];
+    snprintf(nm, sizeof(nm), "mpo[%d]", k);
+    TN_TRY(check_tensor(&mpo[k], nm, TN_F32));
+    if (mpo[k].rank != 4) return fail(TN_ERR_SHAPE_MISMATCH, "%s must be [w_k, w_k+1, d, d]", nm);
+    if (mpo[k].shape[2] != d || mpo[k].shape[3] != d) return fail(TN_ERR_SHAPE_MISMATCH, "%s: physical dims differ from the MPS", nm);
+    if (k == 0) {
+      if (mpo[0].shape[0] != 1) return fail(TN_ERR_SHAPE_MISMATCH, "mpo: first bond must be 1");
+      w.push_back(1);
+    } else if (mpo[k].shape[0] != w.back()) {
+      return fail(TN_ERR_SHAPE_MISMATCH, "mpo: bond %d does not match", k);
+    }
+    if (mpo[k].shape[0] > kMaxW || mpo[k].shape[1] > kMaxW) return fail(TN_ERR_UNSUPPORTED, "MPO bond above %d", kMaxW);
+    w.push_back(mpo[k].shape[1]);
+  }
+  if (w.back() != 1) return fail(TN_ERR_SHAPE_MISMATCH, "mpo: last bond must be 1");
+  if (d > kMaxD) return fail(TN_ERR_UNSUPPORTED, "physical dimension above %d", kMaxD);
+  return TN_OK;
+}
+
+static int32_t check_env_out(const tn_tensor* envs, int32_t n, const std::vector<int64_t>& dims,
+                             const std::vector<int64_t>& w, const char* name) {
+  if (!envs) return TN_OK;
+  for (int k = 0; k <= n; ++k) {
+    char nm[32];
+    snprintf(nm, sizeof(nm), "%s[%d]", name, k);
+    TN_TRY(check_tensor(&envs[k], nm, TN_F32));
+    if (envs[k].rank != 3 || envs[k].shape[0] != dims[k] || envs[k].shape[1] != w[k] || envs[k].shape[2] != dims[k])
+      return fail(TN_ERR_SHAPE_MISMATCH, "%s must be [D_k, w_k, D_k]", nm);
+    if (has_internal_overlap(envs[k])) return fail(TN_ERR_INVALID_ARGUMENT, "%s maps two indices to one address", nm);
+  }
+  return TN_OK;
+}
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+int32_t tn_mps_inner_workspace(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi, size_t* bytes) {
+  if (!bytes) return fail(TN_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  std::vector<int64_t> dp, dq;
+  int64_t d1 = 0, d2 = 0;
+  TN_TRY(check_chain(n_sites, psi, "psi", TN_F32, &dp, &d1));
+  TN_TRY(check_chain(n_sites, phi, "phi", TN_F32, &dq, &d2));
+  if (d1 != d2) return fail(TN_ERR_SHAPE_MISMATCH, "psi and phi have different physical dimensions");
+  *bytes = inner_layout(n_sites, dp, dq, d1).total;
+  return TN_OK;
+}
+
+int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi, double* out2, void* workspace,
+                     size_t ws_bytes, int32_t prec, void* stream) {
+  std::vector<int64_t> dp, dq;
+  int64_t d1 = 0, d2 = 0;
+  TN_TRY(check_chain(n_sites, psi, "psi", TN_F32, &dp, &d1));
+  TN_TRY(check_chain(n_sites, phi, "phi", TN_F32, &dq, &d2));
+  if (d1 != d2) return fail(TN_ERR_SHAPE_MISMATCH, "psi and phi have different physical dimensions");
+  if (!out2) return fail(TN_ERR_INVALID_ARGUMENT, "out2 is NULL");
+  if (prec < 0 || prec > 3) return fail(TN_ERR_UNSUPPORTED, "unknown precision %d", prec);
+  InnerLayout L = inner_layout(n_sites, dp, dq, d1);
+  if (ws_bytes < L.total || !workspace) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", L.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  float* e[2] = {reinterpret_cast<float*>(ws + L.e0), reinterpret_cast<float*>(ws + L.e1)};
+  float* t = reinterpret_cast<float*>(ws + L.t);
+  uint32_t* slots = reinterpret_cast<uint32_t*>(ws + L.slots);
+  hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(n_sites + 1)), dim3(256), 0, st, e[0], slots, n_sites + 1);
+  TN_TRY(hip_check(hipGetLastError(), "mps init"));
+  for (int k = 0; k < n_sites; ++k) TN_TRY(inner_site(psi[k], phi[k], e[k & 1], e[(k + 1) & 1], t, slots, k, prec, st));
+  hipLaunchKernelGGL(mps_finish_kernel, dim3(1), dim3(256), 0, st, e[n_sites & 1], slots, n_sites, out2);
+  return hip_check(hipGetLastError(), "mps finish");
+}
+
+// ----------------------------------------------------------------------------
+// uneven batch
+
+int32_t tn_mps_inner_batched_workspace(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
+                                       const tn_tensor* phi_sites, size_t* bytes);
+int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
+                             const tn_tensor* phi_sites, double* out2, void* workspace, size_t ws_bytes, int32_t prec,
+                             void* stream);
+
+// ----------------------------------------------------------------------------
+// environment sweep
+
+int32_t tn_mps_env_sweep_workspace(int32_t n_sites, const tn_tensor* psi, const tn_tensor* mpo, size_t* bytes) {
+  if (!bytes) return fail(TN_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  std::vector<int64_t> dims, w;
+  int64_t d = 0;
+  TN_TRY(check_chain(n_sites, psi, "psi", TN_F32, &dims, &d));
+  TN_TRY(check_mpo(n_sites, mpo, d, w));
+  *bytes = env_layout(n_sites, dims, w, d).total;
+  return TN_OK;
+}
+
+int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor* mpo, tn_tensor* L_out,
+                         tn_tensor* R_out, double* energy2, int32_t which, void* workspace, size_t ws_bytes, int32_t prec,
+                         void* stream) {
+  std::vector<int64_t> dims, w;
+  int64_t d = 0;
+  TN_TRY(check_chain(n_sites, psi, "psi", TN_F32, &dims, &d));
+  TN_TRY(check_mpo(n_sites, mpo, d, w));
+  TN_TRY(check_env_out(L_out, n_sites, dims, w, "L_out"));
+  TN_TRY(check_env_out(R_out, n_sites, dims, w, "R_out"));
+  if (which < 1 || which > 3) return fail(TN_ERR_INVALID_ARGUMENT, "which must be 1 (left), 2 (right) or 3");
+  if (prec < 0 || prec > 3) return fail(TN_ERR_UNSUPPORTED, "unknown precision %d", prec);
+  for (int k = 0; k < n_sites; ++k)
+    if (dims[k] * std::max(w[k], w[k + 1]) * d * dims[k + 1] >= (1ll << 31))
+      return fail(TN_ERR_UNSUPPORTED, "site %d intermediate larger than 2^31 elements", k);
+  EnvLayout L = env_layout(n_sites, dims, w, d);
+  if (ws_bytes < L.total || !workspace) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", L.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  float* t1 = reinterpret_cast<float*>(ws + L.t1);
+  float* t2 = reinterpret_cast<float*>(ws + L.t2);
+  float* buf[2] = {reinterpret_cast<float*>(ws + L.lbuf0), reinterpret_cast<float*>(ws + L.lbuf1)};
+  float* rbuf[2] = {reinterpret_cast<float*>(ws + L.rbuf0), reinterpret_cast<float*>(ws + L.rbuf1)};
+  const float* l_last = nullptr;
+  const float* r_first = nullptr;
+
+  if (which & 1) {
+    tn_tensor cur = L_out ? L_out[0] : make_view(buf[0], TN_F32, {1, 1, 1});
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, st, static_cast<float*>(cur.data));
+    for (int k = 0; k < n_sites; ++k) {
+      const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
+      tn_tensor T1 = make_view(t1, TN_F32, {da, wl, d, db});
+      tn_tensor T2 = make_view(t2, TN_F32, {da, d, wr, db});
+      tn_tensor nxt = L_out ? L_out[k + 1] : make_view(buf[(k + 1) & 1], TN_F32, {db, wr, db});
+      GemmDesc g;
+      const int32_t a1[1] = {2}, b1[1] = {0};
+      TN_TRY(plan_gemm(cur, psi[k], 1, a1, b1, T1, g));
+      TN_TRY(launch_gemm(g, prec, st));
+      const tn_tensor& W = mpo[k];
+      hipLaunchKernelGGL(wstep_left_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
+                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                         (int)db, (int)wl, (int)wr, (int)d);
+      TN_TRY(hip_check(hipGetLastError(), "wstep left"));
+      const int32_t a3[2] = {0, 1}, b3[2] = {0, 1};
+      TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
+      TN_TRY(launch_gemm(g, prec, st));
+      cur = nxt;
+    }
+    l_last = static_cast<const float*>(cur.data);
+  }
+  if (which & 2) {
+    tn_tensor cur = R_out ? R_out[n_sites] : make_view(rbuf[n_sites & 1], TN_F32, {1, 1, 1});
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, st, static_cast<float*>(cur.data));
+    for (int k = n_sites - 1; k >= 0; --k) {
+      const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
+      tn_tensor T1 = make_view(t1, TN_F32, {da, d, db, wr});
+      tn_tensor T2 = make_view(t2, TN_F32, {wl, da, d, db});
+      tn_tensor nxt = R_out ? R_out[k] : make_view(rbuf[k & 1], TN_F32, {da, wl, da});
+      GemmDesc g;
+      const int32_t a1[1] = {2}, b1[1] = {2};
+      TN_TRY(plan_gemm(psi[k], cur, 1, a1, b1, T1, g));
+      TN_TRY(launch_gemm(g, prec, st));
+      const tn_tensor& W = mpo[k];
+      hipLaunchKernelGGL(wstep_right_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
+                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                         (int)db, (int)wl, (int)wr, (int)d);
+      TN_TRY(hip_check(hipGetLastError(), "wstep right"));
+      const int32_t a3[2] = {1, 2}, b3[2] = {2, 3};
+      TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
+      TN_TRY(launch_gemm(g, prec, st));
+      cur = nxt;
+    }
+    r_first = static_cast<const float*>(cur.data);
+  }
+  if (energy2) {
+    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(64), 0, st, l_last, r_first, energy2);
+    TN_TRY(hip_check(hipGetLastError(), "energy"));
+  }
+  return TN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,287 @@
+// ncon network driver (Appendix B): validates the label lists, simulates the
+// contraction sequence on the host, then runs one trace / pairwise
+// contraction / outer product per step.  Intermediates are carved from the
+// caller's workspace; the last step stores straight into the caller's output
+// through a permuted view (the final reorder of the dangling edges).
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "internal.h"
+
+namespace tn {
+
+namespace {
+
+struct Node {
+  std::vector<int32_t> labels;
+  std::vector<int64_t> shape;
+  int input;        // >= 0: caller's node index; -1: intermediate
+  size_t ws_off;    // intermediate: byte offset in the workspace
+};
+
+enum StepKind { STEP_TRACE, STEP_CONTRACT, STEP_OUTER, STEP_COPY };
+
+struct Step {
+  StepKind kind;
+  int x, y;                   // node ids (y unused for trace/copy)
+  std::vector<int32_t> ax, bx;  // trace axes (ax[0], ax[1]) or contracted pairs
+  int result;                 // node id
+};
+
+struct Plan {
+  std::vector<Node> nodes;
+  std::vector<Step> steps;
+  size_t ws_bytes = 0;
+  int final_node = -1;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int32_t build_plan(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels, const int32_t* offsets,
+                   int32_t n_order, const int32_t* order, Plan& plan) {
+  if (n_nodes < 1) return fail(TN_ERR_INVALID_ARGUMENT, "network needs at least one node");
+  if (!nodes || !labels || !offsets) return fail(TN_ERR_INVALID_ARGUMENT, "NULL network description");
+  if (offsets[0] != 0) return fail(TN_ERR_INVALID_ARGUMENT, "offsets[0] must be 0");
+  std::map<int32_t, std::vector<std::pair<int, int>>> where;  // label -> (node, axis)
+  for (int i = 0; i < n_nodes; ++i) {
+    char nm[32];
+    snprintf(nm, sizeof(nm), "nodes[%d]", i);
+    TN_TRY(check_tensor(&nodes[i], nm, TN_F32));
+    if (offsets[i + 1] - offsets[i] != nodes[i].rank)
+      return fail(TN_ERR_INVALID_ARGUMENT, "node %d: %d labels for rank %d", i, offsets[i + 1] - offsets[i], nodes[i].rank);
+    Node n;
+    n.input = i;
+    n.ws_off = 0;
+    for (int a = 0; a < nodes[i].rank; ++a) {
+      int32_t l = labels[offsets[i] + a];
+      n.labels.push_back(l);
+      n.shape.push_back(nodes[i].shape[a]);
+      where[l].push_back({i, a});
+    }
+    plan.nodes.push_back(n);
+  }
+  int n_open = 0;
+  std::vector<int32_t> closed;
+  for (auto& kv : where) {
+    if (kv.first >= 0) {
+      if (kv.second.size() != 2) return fail(TN_ERR_INVALID_ARGUMENT, "label %d appears %zu times", kv.first, kv.second.size());
+      auto p = kv.second[0], q = kv.second[1];
+      if (nodes[p.first].shape[p.second] != nodes[q.first].shape[q.second])
+        return fail(TN_ERR_SHAPE_MISMATCH, "label %d joins axes of different extent", kv.first);
+      closed.push_back(kv.first);
+    } else {
+      if (kv.second.size() != 1) return fail(TN_ERR_INVALID_ARGUMENT, "open label %d repeated", kv.first);
+      ++n_open;
+    }
+  }
+  for (int q = 1; q <= n_open; ++q)
+    if (!where.count(-q)) return fail(TN_ERR_INVALID_ARGUMENT, "open labels must be -1..-%d", n_open);
+  std::vector<int32_t> seq;
+  if (n_order > 0 && order) {
+    std::vector<int32_t> chk(order, order + n_order);
+    std::vector<int32_t> srt = chk;
+    std::sort(srt.begin(), srt.end());
+    if (srt != closed) return fail(TN_ERR_INVALID_ARGUMENT, "order must list every connected label once");
+    seq = chk;
+  } else {
+    seq = closed;
+  }
+
+  std::vector<int> alive;
+  for (int i = 0; i < n_nodes; ++i) alive.push_back(i);
+  auto new_node = [&](std::vector<int32_t> l, std::vector<int64_t> s) {
+    Node n;
+    n.labels = std::move(l);
+    n.shape = std::move(s);
+    n.input = -1;
+    n.ws_off = 0;
+    plan.nodes.push_back(n);
+    return (int)plan.nodes.size() - 1;
+  };
+  std::map<int32_t, bool> done;
+  for (int32_t lab : seq) {
+    if (done[lab]) continue;
+    std::vector<int> hold;
+    for (int id : alive) {
+      auto& L = plan.nodes[id].labels;
+      if (std::find(L.begin(), L.end(), lab) != L.end()) hold.push_back(id);
+    }
+    if (hold.size() == 1) {
+      Node& n = plan.nodes[hold[0]];
+      std::vector<int32_t> ax;
+      for (int a = 0; a < (int)n.labels.size(); ++a)
+        if (n.labels[a] == lab) ax.push_back(a);
+      std::vector<int32_t> nl;
+      std::vector<int64_t> ns;
+      for (int a = 0; a < (int)n.labels.size(); ++a)
+        if (n.labels[a] != lab) {
+          nl.push_back(n.labels[a]);
+          ns.push_back(n.shape[a]);
+        }
+      int x = hold[0];
+      int r = new_node(nl, ns);
+      Step st;
+      st.kind = STEP_TRACE;
+      st.x = x;
+      st.y = -1;
+      st.ax = ax;
+      st.result = r;
+      plan.steps.push_back(st);
+      *std::find(alive.begin(), alive.end(), x) = r;
+      done[lab] = true;
+      continue;
+    }
+    int x = hold[0], y = hold[1];
+    const Node nx = plan.nodes[x], ny = plan.nodes[y];
+    Step st;
+    st.kind = STEP_CONTRACT;
+    st.x = x;
+    st.y = y;
+    std::vector<bool> cx(nx.labels.size(), false), cy(ny.labels.size(), false);
+    for (int a = 0; a < (int)nx.labels.size(); ++a) {
+      int32_t l = nx.labels[a];
+      if (l < 0) continue;
+      for (int b = 0; b < (int)ny.labels.size(); ++b)
+        if (ny.labels[b] == l && !cy[b]) {
+          st.ax.push_back(a);
+          st.bx.push_back(b);
+          cx[a] = cy[b] = true;
+          done[l] = true;
+          break;
+        }
+    }
+    std::vector<int32_t> nl;
+    std::vector<int64_t> ns;
+    for (int a = 0; a < (int)nx.labels.size(); ++a)
+      if (!cx[a]) {
+        nl.push_back(nx.labels[a]);
+        ns.push_back(nx.shape[a]);
+      }
+    for (int b = 0; b < (int)ny.labels.size(); ++b)
+      if (!cy[b]) {
+        nl.push_back(ny.labels[b]);
+        ns.push_back(ny.shape[b]);
+      }
+    if ((int)nl.size() > TN_MAX_RANK) return fail(TN_ERR_UNSUPPORTED, "intermediate rank %zu exceeds %d", nl.size(), TN_MAX_RANK);
+    st.result = new_node(nl, ns);
+    plan.steps.push_back(st);
+    alive.erase(std::find(alive.begin(), alive.end(), x));
+    alive.erase(std::find(alive.begin(), alive.end(), y));
+    alive.push_back(st.result);
+  }
+  // disconnected pieces: outer products in list order
+  while (alive.size() > 1) {
+    int x = alive[0], y = alive[1];
+    std::vector<int32_t> nl = plan.nodes[x].labels;
+    std::vector<int64_t> ns = plan.nodes[x].shape;
+    nl.insert(nl.end(), plan.nodes[y].labels.begin(), plan.nodes[y].labels.end());
+    ns.insert(ns.end(), plan.nodes[y].shape.begin(), plan.nodes[y].shape.end());
+    if ((int)nl.size() > TN_MAX_RANK) return fail(TN_ERR_UNSUPPORTED, "outer product rank exceeds %d", TN_MAX_RANK);
+    Step st;
+    st.kind = STEP_OUTER;
+    st.x = x;
+    st.y = y;
+    st.result = new_node(nl, ns);
+    plan.steps.push_back(st);
+    alive.erase(alive.begin(), alive.begin() + 2);
+    alive.insert(alive.begin(), st.result);
+  }
+  if (plan.steps.empty()) {
+    Step st;
+    st.kind = STEP_COPY;
+    st.x = alive[0];
+    st.y = -1;
+    st.result = new_node(plan.nodes[alive[0]].labels, plan.nodes[alive[0]].shape);
+    plan.steps.push_back(st);
+  }
+  plan.final_node = plan.steps.back().result;
+  // workspace for every intermediate except the final one
+  size_t off = 0;
+  for (auto& st : plan.steps) {
+    if (st.result == plan.final_node) continue;
+    Node& n = plan.nodes[st.result];
+    int64_t cnt = 1;
+    for (int64_t s : n.shape) cnt *= s;
+    n.ws_off = off;
+    off += align256((size_t)cnt * 4);
+  }
+  plan.ws_bytes = off;
+  return TN_OK;
+}
+
+}  // namespace
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+int32_t tn_contract_network_workspace(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels,
+                                      const int32_t* offsets, int32_t n_order, const int32_t* order, size_t* bytes) {
+  if (!bytes) return fail(TN_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  Plan plan;
+  TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
+  *bytes = plan.ws_bytes;
+  return TN_OK;
+}
+
+int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels, const int32_t* offsets,
+                            int32_t n_order, const int32_t* order, tn_tensor* out, void* workspace, size_t ws_bytes,
+                            int32_t prec, void* stream) {
+  Plan plan;
+  TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
+  TN_TRY(check_tensor(out, "out", TN_F32));
+  if (plan.ws_bytes > ws_bytes) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", plan.ws_bytes);
+  if (plan.ws_bytes > 0 && !workspace) return fail(TN_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  const Node& fin = plan.nodes[plan.final_node];
+  const int n_out = (int)fin.labels.size();
+  if (out->rank != n_out) return fail(TN_ERR_SHAPE_MISMATCH, "out rank %d, network has %d open edges", out->rank, n_out);
+  // the final node's axis p holds open label -(q+1): view out with its axes in that order
+  tn_tensor fview;
+  std::memset(&fview, 0, sizeof(fview));
+  fview.data = out->data;
+  fview.dtype = TN_F32;
+  fview.rank = n_out;
+  for (int p = 0; p < n_out; ++p) {
+    int q = -fin.labels[p] - 1;
+    if (out->shape[q] != fin.shape[p]) return fail(TN_ERR_SHAPE_MISMATCH, "out axis %d has the wrong extent", q);
+    fview.shape[p] = fin.shape[p];
+    fview.stride[p] = out->stride[q];
+  }
+  for (int i = 0; i < n_nodes; ++i)
+    if (overlaps(*out, nodes[i])) return fail(TN_ERR_ALIASING, "out overlaps node %d", i);
+  if (plan.ws_bytes > 0) {
+    tn_tensor wsv = make_view(workspace, TN_F32, {(int64_t)(plan.ws_bytes / 4)});
+    if (overlaps(*out, wsv)) return fail(TN_ERR_ALIASING, "out overlaps the workspace");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto view_of = [&](int id) -> tn_tensor {
+    const Node& n = plan.nodes[id];
+    if (id == plan.final_node) return fview;
+    if (n.input >= 0) return nodes[n.input];
+    return contiguous_view(static_cast<char*>(workspace) + n.ws_off, TN_F32, (int32_t)n.shape.size(), n.shape.data());
+  };
+  for (auto& s : plan.steps) {
+    tn_tensor x = view_of(s.x);
+    tn_tensor r = view_of(s.result);
+    if (s.kind == STEP_TRACE) {
+      TN_TRY(tn_trace_edge(&x, s.ax[0], s.ax[1], &r, stream));
+    } else if (s.kind == STEP_CONTRACT) {
+      tn_tensor y = view_of(s.y);
+      TN_TRY(contract_between_impl(&x, &y, (int32_t)s.ax.size(), s.ax.data(), s.bx.data(), &r, prec, st));
+    } else if (s.kind == STEP_OUTER) {
+      tn_tensor y = view_of(s.y);
+      TN_TRY(contract_between_impl(&x, &y, 0, nullptr, nullptr, &r, prec, st));
+    } else {
+      std::vector<AxisSpec> ra, ka;
+      for (int a = 0; a < x.rank; ++a) ra.push_back({x.shape[a], {x.stride[a], 0, r.stride[a]}});
+      TN_TRY(reduce_from_axes(static_cast<const float*>(x.data), nullptr, static_cast<float*>(r.data), ra, ka, false, st));
+    }
+  }
+  return TN_OK;
+}
+
+}  // extern "C"

@@ -136,23 +136,34 @@ def random_orthogonal(n, rng):
     return q * np.sign(np.diag(r))[None, :]
 
 
-def product_state_mps(local_vectors, dims, rng):
-    """Product state embedded in bond dims `dims` and hidden by random orthogonal gauges.
+def product_state_mps(local_vectors, dims, rng, n_gauges=3):
+    """Product state written with full-rank dense bond matrices.
 
-    Site k carries the local vector in entry [0, :, 0] of a zero tensor of
-    shape [D_k, d, D_{k+1}]; then A_k <- G_k^T A_k G_{k+1} with random
-    orthogonal G_k (G_0 = G_N = [[1]]).  The state is unchanged, so its norm
-    and energies keep their closed forms while every entry becomes dense.
+    A_k[a, s, b] = v_k[s] M_k[a, b] with M_k = G_k^T E_k G_{k+1}, where E_k
+    is the D_k x D_{k+1} identity embedding and G_k are random orthogonal
+    matrices (G_0 = G_N = [[1]]; a few distinct ones are cycled along the
+    chain).  The bond matrices telescope, M_0 M_1 ... M_{N-1} = [[1]], so the
+    state is exactly the product of the local vectors: its norm and energies
+    keep their closed forms while every site tensor is dense.
     """
     n = len(local_vectors)
-    d = len(local_vectors[0])
-    gs = [np.ones((1, 1))] + [random_orthogonal(dims[k], rng) for k in range(1, n)] + [np.ones((1, 1))]
+    gauges, mats = {}, {}
+
+    def gauge(k):
+        if dims[k] == 1:
+            return np.ones((1, 1))
+        key = (dims[k], k % n_gauges)
+        if key not in gauges:
+            gauges[key] = random_orthogonal(dims[k], rng)
+        return gauges[key]
+
     sites = []
     for k in range(n):
-        a = np.zeros((dims[k], d, dims[k + 1]))
-        a[0, :, 0] = local_vectors[k]
-        a = np.einsum("ia,asb,bj->isj", gs[k].T, a, gs[k + 1])
-        sites.append(a)
+        key = (dims[k], dims[k + 1], k % n_gauges if dims[k] > 1 else -1, (k + 1) % n_gauges if dims[k + 1] > 1 else -1)
+        if key not in mats:
+            mats[key] = gauge(k).T @ np.eye(dims[k], dims[k + 1]) @ gauge(k + 1)
+        v = np.asarray(local_vectors[k], dtype=np.float64)
+        sites.append(mats[key][:, None, :] * v[None, :, None])
     return sites
 
 

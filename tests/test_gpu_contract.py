@@ -1,0 +1,351 @@
+"""GPU parity of the pairwise contraction, trace, outer product and ncon
+network entry points against the FP64 oracle.
+
+Tolerances (relative Frobenius error against the oracle run on the same
+FP32-rounded inputs): FP32 1e-5 and SPLIT_BF16 1e-6 (the stated accuracy
+targets), SPLIT_BF16_3P 1e-4 and plain BF16 2e-2 (reported precisions: the
+bounds only catch gross errors).  Element-wise, every output must also be
+within tol * (|A| |B|)_ij, the scale of the sum that produced it.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1905_01330_amd as tn
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+TOL = {"fp32": 1e-5, "split_bf16": 1e-6, "split_bf16_3p": 1e-4, "bf16": 2e-2}
+PRECS = list(TOL)
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32)
+
+
+def gpu(x):
+    return torch.tensor(np.asarray(x, dtype=np.float32), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+def check(got, ref, scale, tol, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    den = np.linalg.norm(ref.ravel())
+    rel = np.linalg.norm((got - ref).ravel()) / (den if den > 0 else 1.0)
+    assert rel <= tol, f"{what}: relative error {rel:.3e} > {tol:.1e}"
+    bound = tol * 4 * scale + 1e-30
+    bad = np.abs(got - ref) > bound
+    assert not bad.any(), f"{what}: {bad.sum()} elements outside the element-wise bound"
+    return rel
+
+
+def abs_scale(a, b, pa, pb):
+    return oracle.tensordot(np.abs(a), np.abs(b), pa, pb)
+
+
+# ---------------------------------------------------------------------------
+# the paper's examples
+
+
+def test_paper_examples_on_gpu():
+    g = GOLDEN["ones_dot"]
+    c = tn.contract_between(gpu(g["a"]), gpu(g["b"]), [0], [0])
+    assert float(host(c)) == g["value"]
+    c = tn.contract_network([gpu(g["a"]), gpu(g["b"])], [[0], [0]])
+    assert float(host(c)) == g["value"]
+    g = GOLDEN["outer_shape"]
+    rng = np.random.default_rng(1)
+    a, b = f32(rng.standard_normal(g["shape_a"])), f32(rng.standard_normal(g["shape_b"]))
+    c = tn.outer_product(gpu(a), gpu(b))
+    assert list(c.shape) == g["shape_out"]
+    np.testing.assert_array_equal(host(c), oracle.outer_product(a, b).astype(np.float32))
+    g = GOLDEN["ncon_matmul"]
+    a, b = f32(rng.standard_normal((2, 2))), f32(rng.standard_normal((2, 2)))
+    c = tn.contract_network([gpu(a), gpu(b)], g["labels"])
+    assert np.linalg.norm(host(c) - a.astype(np.float64) @ b.astype(np.float64)) < 1e-6
+    c = tn.contract_network([gpu(np.eye(2)), gpu(np.eye(2))], [[0, 1], [0, 1]])
+    assert float(host(c)) == 2.0
+    h = np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0)
+    out = tn.contract_network([gpu([1.0, 0.0])] + [gpu(h)] * 5, [[0]] + [[i + 1, i] for i in range(4)] + [[-1, 4]])
+    np.testing.assert_allclose(host(out), [2 ** -0.5, 2 ** -0.5], rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# fuzzed pairwise contractions
+
+
+def random_case(rng, max_dim=9, big=False):
+    ra = int(rng.integers(1, 6))
+    rb = int(rng.integers(1, 6))
+    npairs = int(rng.integers(1, min(ra, rb) + 1))
+    pa = [int(x) for x in rng.permutation(ra)[:npairs]]
+    pb = [int(x) for x in rng.permutation(rb)[:npairs]]
+    hi = 80 if big else max_dim
+    sa = [int(rng.integers(1, hi)) for _ in range(ra)]
+    sb = [int(rng.integers(1, hi)) for _ in range(rb)]
+    for i, j in zip(pa, pb):
+        sb[j] = sa[i]
+    # keep sizes moderate
+    while np.prod(sa) > 400_000:
+        k = int(np.argmax(sa))
+        sa[k] = max(1, sa[k] // 2)
+        for i, j in zip(pa, pb):
+            sb[j] = sa[i]
+    while np.prod(sb) > 400_000:
+        k = int(np.argmax(sb))
+        sb[k] = max(1, sb[k] // 2)
+        for i, j in zip(pa, pb):
+            sa[i] = sb[j]
+    return sa, sb, pa, pb
+
+
+def permuted_input(x, rng):
+    """The same tensor as a non-contiguous view: stored transposed, viewed back."""
+    if x.ndim < 2:
+        return gpu(x)
+    perm = [int(p) for p in rng.permutation(x.ndim)]
+    stored = gpu(np.transpose(x, perm).copy())
+    inv = np.argsort(perm)
+    return stored.permute(*[int(i) for i in inv])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed", range(12))
+def test_fuzz_contract_between(prec, seed):
+    rng = np.random.default_rng(500 + seed)
+    sa, sb, pa, pb = random_case(rng, big=seed % 3 == 0)
+    a = f32(rng.standard_normal(sa))
+    b = f32(rng.standard_normal(sb))
+    ga = permuted_input(a, rng) if seed % 2 else gpu(a)
+    gb = permuted_input(b, rng) if seed % 4 in (1, 2) else gpu(b)
+    ref = oracle.tensordot(a, b, pa, pb)
+    out_shape = ref.shape
+    if len(out_shape) >= 2 and seed % 3 == 1:
+        perm = [int(p) for p in rng.permutation(len(out_shape))]
+        store = torch.empty([out_shape[p] for p in perm], device=DEV)
+        out = store.permute(*[int(i) for i in np.argsort(perm)])
+    else:
+        out = torch.empty(out_shape, device=DEV)
+    tn.contract_between(ga, gb, pa, pb, out=out, prec=prec)
+    check(host(out), ref, abs_scale(a, b, pa, pb), TOL[prec], f"{sa}x{sb} pairs {pa}/{pb}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ragged_gemm_all_tiles(prec):
+    rng = np.random.default_rng(7)
+    a = f32(rng.standard_normal((197, 301)))
+    b = f32(rng.standard_normal((301, 259)))
+    ref = a.astype(np.float64) @ b.astype(np.float64)
+    scale = np.abs(a).astype(np.float64) @ np.abs(b).astype(np.float64)
+    try:
+        for cfg in range(tn.tune_num_configs()):
+            tn.tune_force_config(cfg)
+            out = tn.contract_between(gpu(a), gpu(b), [1], [0], prec=prec)
+            check(host(out), ref, scale, TOL[prec], f"tile config {cfg}")
+    finally:
+        tn.tune_force_config(-1)
+
+
+@pytest.mark.parametrize("layout", ["kk", "mk", "km", "mm", "gen"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_operand_layouts(layout, prec):
+    """A stored M-major or K-major, B stored N-major or K-major, and a gather case."""
+    rng = np.random.default_rng(11)
+    M, K, N = 260, 132, 196
+    a = f32(rng.standard_normal((M, K)))
+    b = f32(rng.standard_normal((K, N)))
+    ga = gpu(a) if layout[0] == "k" else gpu(a.T.copy()).t()
+    gb = gpu(b.T.copy()).t() if layout[-1] == "k" else gpu(b)
+    if layout == "gen":
+        big = gpu(np.zeros((M, 3 * K), dtype=np.float32))
+        big[:, ::3] = gpu(a)
+        ga = big[:, ::3]
+    out = tn.contract_between(ga, gb, [1], [0], prec=prec)
+    ref = a.astype(np.float64) @ b.astype(np.float64)
+    check(host(out), ref, np.abs(a).astype(np.float64) @ np.abs(b), TOL[prec], layout)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "bf16"])
+def test_rank0_and_rank1_results(prec):
+    rng = np.random.default_rng(13)
+    v = f32(rng.standard_normal(100_003))
+    w = f32(rng.standard_normal(100_003))
+    d = tn.contract_between(gpu(v), gpu(w), [0], [0], prec=prec)
+    ref = float(np.dot(v.astype(np.float64), w.astype(np.float64)))
+    assert d.dim() == 0
+    tol = TOL[prec] if prec != "bf16" else 2e-2
+    assert abs(float(host(d)) - ref) <= tol * float(np.dot(np.abs(v), np.abs(w)))
+    m = f32(rng.standard_normal((300, 517)))
+    x = f32(rng.standard_normal(517))
+    out = tn.contract_between(gpu(m), gpu(x), [1], [0], prec=prec)
+    check(host(out), m.astype(np.float64) @ x, np.abs(m) @ np.abs(x), tol, "matvec")
+    out = tn.contract_between(gpu(x), gpu(m.T.copy()), [0], [0], prec=prec)
+    check(host(out), m.astype(np.float64) @ x, np.abs(m) @ np.abs(x), tol, "vecmat")
+    t3 = f32(rng.standard_normal((5, 7, 6)))
+    u3 = f32(rng.standard_normal((6, 5, 7)))
+    out = tn.contract_between(gpu(t3), gpu(u3), [0, 1, 2], [1, 2, 0], prec=prec)
+    ref = oracle.tensordot(t3, u3, [0, 1, 2], [1, 2, 0])
+    assert abs(float(host(out)) - float(ref)) <= tol * float(oracle.tensordot(np.abs(t3), np.abs(u3), [0, 1, 2], [1, 2, 0]))
+
+
+def test_scalar_operands_and_unit_dims():
+    s = gpu(np.float32(3.0).reshape(()))
+    v = gpu(np.arange(5, dtype=np.float32))
+    out = tn.contract_between(s, v, [], [])
+    np.testing.assert_array_equal(host(out), 3.0 * np.arange(5))
+    a = f32(np.random.default_rng(3).standard_normal((1, 4, 1, 3)))
+    b = f32(np.random.default_rng(4).standard_normal((3, 1, 2)))
+    out = tn.contract_between(gpu(a), gpu(b), [3, 2], [0, 1])
+    check(host(out), oracle.tensordot(a, b, [3, 2], [0, 1]), abs_scale(a, b, [3, 2], [0, 1]), 1e-5)
+
+
+def test_deterministic_results():
+    rng = np.random.default_rng(17)
+    a, b = gpu(rng.standard_normal((333, 444))), gpu(rng.standard_normal((444, 222)))
+    for prec in ("fp32", "split_bf16"):
+        x = host(tn.contract_between(a, b, [1], [0], prec=prec))
+        y = host(tn.contract_between(a, b, [1], [0], prec=prec))
+        np.testing.assert_array_equal(x, y)
+
+
+def test_autotune_path_matches():
+    rng = np.random.default_rng(19)
+    a, b = f32(rng.standard_normal((384, 256))), f32(rng.standard_normal((256, 320)))
+    ref = a.astype(np.float64) @ b
+    try:
+        tn.tune_set_level(1)
+        out = tn.contract_between(gpu(a), gpu(b), [1], [0], prec="split_bf16")
+        assert 0 <= tn.tune_last_choice() < tn.tune_num_configs()
+        check(host(out), ref, np.abs(a) @ np.abs(b), 1e-6, "autotuned")
+    finally:
+        tn.tune_set_level(0)
+
+
+# ---------------------------------------------------------------------------
+# headline shapes at full size (chi = 1024, MPO bond 5): sampled outputs
+
+
+def sampled_check(a, b, pa, pb, out, n_samples, tol, seed):
+    rng = np.random.default_rng(seed)
+    free_a = [i for i in range(a.ndim) if i not in pa]
+    free_b = [j for j in range(b.ndim) if j not in pb]
+    got = out.cpu().double().numpy()
+    am = np.transpose(a, free_a + pa).reshape(-1, int(np.prod([a.shape[i] for i in pa])))
+    bm = np.transpose(b, pb + free_b).reshape(int(np.prod([b.shape[j] for j in pb])), -1)
+    gm = got.reshape(am.shape[0], bm.shape[1])
+    rows = rng.integers(0, am.shape[0], n_samples)
+    cols = rng.integers(0, bm.shape[1], n_samples)
+    ref = np.einsum("ik,ki->i", am[rows].astype(np.float64), bm[:, cols].astype(np.float64))
+    scale = np.einsum("ik,ki->i", np.abs(am[rows]).astype(np.float64), np.abs(bm[:, cols]).astype(np.float64))
+    err = np.abs(gm[rows, cols] - ref)
+    assert np.all(err <= tol * scale), float(np.max(err / scale))
+    return float(np.linalg.norm(gm[rows, cols] - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_headline_tensordots_full_size(prec):
+    rng = np.random.default_rng(301)
+    L = f32(rng.standard_normal((1024, 5, 1024)))
+    A = f32(rng.standard_normal((1024, 2, 1024)) / np.sqrt(2048))
+    t1 = tn.contract_between(gpu(L), gpu(A), [2], [0], prec=prec)        # M=5120 K=1024 N=2048
+    assert tuple(t1.shape) == (1024, 5, 2, 1024)
+    sampled_check(L, A, [2], [0], t1, 4000, TOL[prec], 1)
+    T2 = f32(rng.standard_normal((1024, 2, 5, 1024)))
+    t3 = tn.contract_between(gpu(A), gpu(T2), [0, 1], [0, 1], prec=prec)  # M=1024 K=2048 N=5120
+    assert tuple(t3.shape) == (1024, 5, 1024)
+    sampled_check(A, T2, [0, 1], [0, 1], t3, 4000, TOL[prec], 2)
+
+
+# ---------------------------------------------------------------------------
+# trace and outer products
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_trace_edge(seed):
+    rng = np.random.default_rng(700 + seed)
+    r = int(rng.integers(2, 6))
+    shape = [int(rng.integers(1, 9)) for _ in range(r)]
+    i, j = [int(x) for x in rng.permutation(r)[:2]]
+    shape[j] = shape[i] = max(shape[i], 2) if seed % 2 else shape[i]
+    a = f32(rng.standard_normal(shape))
+    ga = permuted_input(a, rng)
+    out = tn.trace_edge(ga, i, j)
+    ref = oracle.trace_edge(a, i, j)
+    check(host(out), ref, oracle.trace_edge(np.abs(a), i, j), 1e-6)
+
+
+def test_trace_large_scalar():
+    a = f32(np.random.default_rng(1).standard_normal((3001, 3001)))
+    out = tn.trace_edge(gpu(a), 0, 1)
+    ref = float(np.trace(a.astype(np.float64)))
+    assert abs(float(host(out)) - ref) < 1e-6 * float(np.sum(np.abs(np.diag(a))))
+
+
+def test_outer_product_strided():
+    rng = np.random.default_rng(23)
+    a = f32(rng.standard_normal((33, 7)))
+    b = f32(rng.standard_normal((5, 65)))
+    ga = gpu(a.T.copy()).t()
+    out = tn.outer_product(ga, gpu(b))
+    np.testing.assert_array_equal(host(out), oracle.outer_product(a, b).astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# networks
+
+
+def _small_network(rng):
+    t0 = f32(rng.standard_normal((2, 3, 3, 2)))
+    t1 = f32(rng.standard_normal((2, 2, 3)))
+    t2 = f32(rng.standard_normal((2, 2, 2, 2)))
+    t3 = f32(rng.standard_normal((2, 2)))
+    return [t0, t1, t2, t3], [[0, 9, 9, 1], [0, 2, -2], [1, 2, 3, -1], [3, -3]]
+
+
+def test_network_all_orders():
+    rng = np.random.default_rng(31)
+    ts, ls = _small_network(rng)
+    ref = oracle.contract_network(ts, ls)
+    gts = [gpu(t) for t in ts]
+    for order in itertools.permutations([0, 1, 2, 3, 9]):
+        out = tn.contract_network(gts, ls, order=list(order))
+        np.testing.assert_allclose(host(out), ref, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_network_mps_ring(prec):
+    # a periodic 6-site MPS contracted with itself: a closed network (scalar)
+    rng = np.random.default_rng(37)
+    n, chi = 6, 24
+    sites = [f32(rng.standard_normal((chi, 2, chi)) / np.sqrt(2 * chi)) for _ in range(n)]
+    ts = sites + sites
+    labels = [[k, 100 + k, (k + 1) % n] for k in range(n)] + [[10 + k, 100 + k, 10 + (k + 1) % n] for k in range(n)]
+    ref = oracle.contract_network(ts, labels)
+    out = tn.contract_network([gpu(t) for t in ts], labels, prec=prec)
+    assert abs(float(host(out)) / float(ref) - 1) < 10 * TOL[prec]
+
+
+def test_network_single_node_permutation_and_disconnected():
+    rng = np.random.default_rng(41)
+    a = f32(rng.standard_normal((3, 4, 5)))
+    out = tn.contract_network([gpu(a)], [[-2, -3, -1]])
+    np.testing.assert_array_equal(host(out), np.transpose(a, (2, 0, 1)))
+    b = f32(rng.standard_normal(6))
+    out = tn.contract_network([gpu(a), gpu(b)], [[-2, -4, -1], [-3]])
+    np.testing.assert_array_equal(host(out), oracle.contract_network([a, b], [[-2, -4, -1], [-3]]).astype(np.float32))
+    c = f32(rng.standard_normal((4, 4)))
+    out = tn.contract_network([gpu(c)], [[0, 0]])
+    assert abs(float(host(out)) - float(np.trace(c))) < 1e-5
