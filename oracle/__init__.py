@@ -23,6 +23,8 @@ from .mps import (  # noqa: F401
     mps_inner_value,
     left_canonicalize,
     env_sweep,
+    env_left_step,
+    env_right_step,
     mps_to_dense,
     mpo_to_dense,
 )

@@ -121,6 +121,22 @@ def left_canonicalize(mps):
     return out, math.log(norm)
 
 
+def env_left_step(l, a, w):
+    """L_{k+1}[b', v, b] = sum A[a', t, b'] W[u, v, t, s] L_k[a', u, a] A[a, s, b]."""
+    t1 = tensordot(l, a, [2], [0])                     # [a', u, s, b]
+    t2 = tensordot(t1, w, [1, 2], [0, 3])              # [a', b, v, t]
+    out = tensordot(a, t2, [0, 1], [0, 3])             # [b', b, v]
+    return np.transpose(out, (0, 2, 1)).copy()         # [b', v, b]
+
+
+def env_right_step(r, a, w):
+    """R_k[a', u, a] = sum A[a', t, b'] W[u, v, t, s] R_{k+1}[b', v, b] A[a, s, b]."""
+    t1 = tensordot(a, r, [2], [2])                     # [a, s, b', v]
+    t2 = tensordot(t1, w, [1, 3], [3, 1])              # [a, b', u, t]
+    out = tensordot(a, t2, [1, 2], [3, 1])             # [a', a, u]
+    return np.transpose(out, (0, 2, 1)).copy()         # [a', u, a]
+
+
 def env_sweep(psi, mpo, want_left=True, want_right=True):
     """Left and right environments of <psi|H|psi> and the energy from each side.
 
@@ -136,20 +152,12 @@ def env_sweep(psi, mpo, want_left=True, want_right=True):
     if want_left:
         ls = [np.ones((1, 1, 1))]
         for k in range(n):
-            a, w = psi[k], mpo[k]
-            t1 = tensordot(ls[-1], a, [2], [0])        # [a', u, s, b]
-            t2 = tensordot(t1, w, [1, 2], [0, 3])      # [a', b, v, t]
-            l = tensordot(a, t2, [0, 1], [0, 3])       # [b', b, v]
-            ls.append(np.transpose(l, (0, 2, 1)).copy())  # [b', v, b]
+            ls.append(env_left_step(ls[-1], psi[k], mpo[k]))
         e_left = float(ls[-1][0, 0, 0])
     if want_right:
         rs = [None] * (n + 1)
         rs[n] = np.ones((1, 1, 1))
         for k in range(n - 1, -1, -1):
-            a, w = psi[k], mpo[k]
-            t1 = tensordot(a, rs[k + 1], [2], [2])     # [a, s, b', v]
-            t2 = tensordot(t1, w, [1, 3], [3, 1])      # [a, b', u, t]
-            r = tensordot(a, t2, [1, 2], [3, 1])       # [a', a, u]
-            rs[k] = np.transpose(r, (0, 2, 1)).copy()  # [a', u, a]
+            rs[k] = env_right_step(rs[k + 1], psi[k], mpo[k])
         e_right = float(rs[0][0, 0, 0])
     return ls, rs, e_left, e_right

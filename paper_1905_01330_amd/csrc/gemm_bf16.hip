@@ -2,6 +2,6 @@
 #include "gemm_inst.h"
 
 namespace tn {
-GemmFn gemm_fn_bf16(int cfg) { return gemm_fn<P_BF16>(cfg); }
+GemmFn gemm_fn_bf16(int cfg, int variant) { return gemm_fn<P_BF16>(cfg, variant); }
 GroupedFn grouped_fn_bf16(int cfg) { return grouped_fn<P_BF16>(cfg); }
 }  // namespace tn

@@ -2,6 +2,6 @@
 #include "gemm_inst.h"
 
 namespace tn {
-GemmFn gemm_fn_fp32(int cfg) { return gemm_fn<P_FP32>(cfg); }
+GemmFn gemm_fn_fp32(int cfg, int variant) { return gemm_fn<P_FP32>(cfg, variant); }
 GroupedFn grouped_fn_fp32(int cfg) { return grouped_fn<P_FP32>(cfg); }
 }  // namespace tn

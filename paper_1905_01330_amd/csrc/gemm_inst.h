@@ -7,13 +7,15 @@
 
 namespace tn {
 
-template <int P, int BM, int BN, int BK, int WM, int WN>
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE, int BMODE>
 __global__ void __launch_bounds__(WM* WN * 64) gemm_kernel(const GemmDesc d) {
-  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN>::lds_bytes];
+  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::lds_bytes];
   __shared__ Group gk;
-  copy_group(gk, d.gk);
-  __syncthreads();
-  GemmTile<P, BM, BN, BK, WM, WN>::run(d, gk, blockIdx.x, blockIdx.z, smem);
+  if constexpr (AMODE < 0 || BMODE < 0) {
+    copy_group(gk, d.gk);
+    __syncthreads();
+  }
+  GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::run(d, gk, blockIdx.x, blockIdx.z, smem);
 }
 
 // Grouped launch: the workgroup finds its problem by binary search over the
@@ -22,7 +24,7 @@ __global__ void __launch_bounds__(WM* WN * 64) gemm_kernel(const GemmDesc d) {
 template <int P, int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(WM* WN * 64)
     gemm_grouped_kernel(const Gemm2D* probs, const int32_t* tile_start, int32_t n_probs) {
-  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN>::lds_bytes];
+  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, -1, -1>::lds_bytes];
   __shared__ GemmDesc sd;
   __shared__ int32_t s_prob;
   const int bid = blockIdx.x;
@@ -74,21 +76,33 @@ __global__ void __launch_bounds__(WM* WN * 64)
     d.c_mode = (p.scm == 1 && p.M % 4 == 0 && p.scn % 4 == 0 && al(p.c)) ? STORE_MVEC : STORE_SCALAR;
   }
   __syncthreads();
-  GemmTile<P, BM, BN, BK, WM, WN>::run(sd, sd.gk, bid - tile_start[s_prob], 0, smem);
+  GemmTile<P, BM, BN, BK, WM, WN, -1, -1>::run(sd, sd.gk, bid - tile_start[s_prob], 0, smem);
 }
 
 
-template <int P>
-GemmFn gemm_fn(int cfg) {
+template <int P, int AM, int BM_>
+GemmFn gemm_fn_modes(int cfg) {
   switch (cfg) {
-    case 0: return gemm_kernel<P, 256, 128, 16, 2, 2>;
-    case 1: return gemm_kernel<P, 128, 256, 16, 2, 2>;
-    case 2: return gemm_kernel<P, 128, 128, 16, 2, 2>;
-    case 3: return gemm_kernel<P, 128, 128, 32, 2, 2>;
-    case 4: return gemm_kernel<P, 128, 64, 32, 2, 2>;
-    case 5: return gemm_kernel<P, 64, 128, 32, 2, 2>;
-    case 6: return gemm_kernel<P, 64, 64, 32, 2, 2>;
-    default: return gemm_kernel<P, 32, 32, 32, 1, 1>;
+    case 0: return gemm_kernel<P, 256, 128, 16, 2, 2, AM, BM_>;
+    case 1: return gemm_kernel<P, 128, 256, 16, 2, 2, AM, BM_>;
+    case 2: return gemm_kernel<P, 128, 128, 16, 2, 2, AM, BM_>;
+    case 3: return gemm_kernel<P, 128, 128, 32, 2, 2, AM, BM_>;
+    case 4: return gemm_kernel<P, 128, 64, 32, 2, 2, AM, BM_>;
+    case 5: return gemm_kernel<P, 64, 128, 32, 2, 2, AM, BM_>;
+    case 6: return gemm_kernel<P, 64, 64, 32, 2, 2, AM, BM_>;
+    default: return gemm_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
+  }
+}
+
+// variant 0: run-time gathers; 1..4: fast gathers (A, B) = (K,K) (K,MN) (MN,K) (MN,MN)
+template <int P>
+GemmFn gemm_fn(int cfg, int variant) {
+  switch (variant) {
+    case 1: return gemm_fn_modes<P, LOAD_KVEC, LOAD_KVEC>(cfg);
+    case 2: return gemm_fn_modes<P, LOAD_KVEC, LOAD_MNVEC>(cfg);
+    case 3: return gemm_fn_modes<P, LOAD_MNVEC, LOAD_KVEC>(cfg);
+    case 4: return gemm_fn_modes<P, LOAD_MNVEC, LOAD_MNVEC>(cfg);
+    default: return gemm_fn_modes<P, -1, -1>(cfg);
   }
 }
 

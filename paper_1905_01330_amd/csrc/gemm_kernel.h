@@ -58,34 +58,49 @@ struct LdsOperand {
   static constexpr int bytes = PrecInfo<P>::bf ? R * LDH * 2 * PrecInfo<P>::planes : R * LDK * 4;
 };
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+// Split two FP32 values into BF16 terms x = x0 + x1 + x2 (each rounded to
+// nearest even; exact for normal inputs).  The pair is converted with one
+// packed conversion per term; the terms come back packed two to a dword.
+template <int NPL>
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t (&t)[3]) {
+  f32x2_t x = {a, b};
+  uint32_t u = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2_t));
+  t[0] = u;
+  if constexpr (NPL >= 2) {
+    const float ra = a - __uint_as_float(u << 16);
+    const float rb = b - __uint_as_float(u & 0xffff0000u);
+    f32x2_t r = {ra, rb};
+    u = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2_t));
+    t[1] = u;
+    if constexpr (NPL >= 3) {
+      f32x2_t r2 = {ra - __uint_as_float(u << 16), rb - __uint_as_float(u & 0xffff0000u)};
+      t[2] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r2, bf16x2_t));
+    }
+  }
+}
+
 template <int P, int R, int BK>
 __device__ inline void lds_put4(char* base, int row, int kcol, f32x4_t v) {
   if constexpr (!PrecInfo<P>::bf) {
     float* p = reinterpret_cast<float*>(base);
     *reinterpret_cast<f32x4_t*>(p + row * LdsOperand<P, R, BK>::LDK + kcol) = v;
   } else {
+    constexpr int NPL = PrecInfo<P>::planes;
     constexpr int LDH = LdsOperand<P, R, BK>::LDH;
     constexpr int plane = R * LDH;
     __bf16* h = reinterpret_cast<__bf16*>(base) + row * LDH + kcol;
-    bf16x4_t t0, t1, t2;
+    uint32_t lo[3], hi[3];
+    split_pair<NPL>(v[0], v[1], lo);
+    split_pair<NPL>(v[2], v[3], hi);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float x = v[q];
-      __bf16 x0 = (__bf16)x;
-      t0[q] = x0;
-      if constexpr (PrecInfo<P>::planes >= 2) {
-        float r1 = x - (float)x0;
-        __bf16 x1 = (__bf16)r1;
-        t1[q] = x1;
-        if constexpr (PrecInfo<P>::planes >= 3) {
-          float r2 = r1 - (float)x1;
-          t2[q] = (__bf16)r2;
-        }
-      }
+    for (int p = 0; p < NPL; ++p) {
+      u32x2_t w = {lo[p], hi[p]};
+      *reinterpret_cast<u32x2_t*>(h + p * plane) = w;
     }
-    *reinterpret_cast<bf16x4_t*>(h) = t0;
-    if constexpr (PrecInfo<P>::planes >= 2) *reinterpret_cast<bf16x4_t*>(h + plane) = t1;
-    if constexpr (PrecInfo<P>::planes >= 3) *reinterpret_cast<bf16x4_t*>(h + 2 * plane) = t2;
   }
 }
 
@@ -150,7 +165,7 @@ struct OperandLoader {
 #pragma unroll
       for (int v = 0; v < VM; ++v) {
         int idx = tid + v * NT;
-        int row = row0 + (idx % (R / 4)) * 4;
+        int row = row0 + (idx / KQ) * 4;
         rowoff[v] = 0;
         if (idx < NMV && row < nrows) {
           int64_t o[1];
@@ -190,7 +205,7 @@ struct OperandLoader {
 #pragma unroll
       for (int v = 0; v < VM; ++v) {
         int idx = tid + v * NT;
-        int k = k0 + (idx / (R / 4)) * 4;
+        int k = k0 + (idx % KQ) * 4;
         // the four k of the micro-block: one offset and the innermost stride
         // when they share the innermost K run, else one offset each
         const int last = gk.n - 1;
@@ -225,20 +240,112 @@ struct OperandLoader {
 #pragma unroll
       for (int v = 0; v < VK; ++v) {
         int idx = tid + v * NT;
-        if (idx < NKV) lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[v] * scale);
+        if (idx < NKV) lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[v]);
       }
     } else {
 #pragma unroll
       for (int v = 0; v < VM; ++v) {
         int idx = tid + v * NT;
         if (idx < NMV) {
-          int r0 = (idx % (R / 4)) * 4;
-          int kc = (idx / (R / 4)) * 4;
+          int r0 = (idx / KQ) * 4;
+          int kc = (idx % KQ) * 4;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             f32x4_t t = {st[4 * v + 0][i], st[4 * v + 1][i], st[4 * v + 2][i], st[4 * v + 3][i]};
-            lds_put4<P, R, BK>(lds, r0 + i, kc, t * scale);
+            lds_put4<P, R, BK>(lds, r0 + i, kc, t);
           }
+        }
+      }
+    }
+  }
+};
+
+// Fast gather for a single merged contracted axis (the common case after
+// axis merging): each thread keeps one pointer per micro-block that advances
+// by a constant every stage; rows past the end are clamped to the last valid
+// row (their products only reach output rows that are never stored), so
+// only the last, partial K stage carries bounds checks.
+//   MODE = LOAD_KVEC : k is the unit-stride axis, 1 x 4 micro-blocks
+//   MODE = LOAD_MNVEC: the row axis is unit-stride, 4 x 4 micro-blocks,
+//                      transposed in registers before the LDS store
+template <int P, int R, int BK, int NT, int MODE>
+struct FastLoader {
+  static constexpr int KQ = BK / 4;
+  static constexpr int NMB = MODE == LOAD_KVEC ? R * BK / 4 : R * BK / 16;
+  static constexpr int NV = (NMB + NT - 1) / NT;
+  static constexpr bool EXACT = NMB % NT == 0;
+  static constexpr int NREG = MODE == LOAD_KVEC ? NV : 4 * NV;
+
+  f32x4_t st[NREG];
+  const float* ptr[NV];
+  int kq[NV];
+  int64_t sk;
+  int K;
+
+  __device__ __forceinline__ void init(const float* base, const Group& grows, int row0, int nrows, int64_t sk_, int K_) {
+    sk = sk_;
+    K = K_;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = tid + v * NT;
+      int row, k;
+      if constexpr (MODE == LOAD_KVEC) {
+        row = row0 + idx / KQ;
+        k = (idx % KQ) * 4;
+        row = row < nrows ? row : nrows - 1;
+      } else {
+        // k-chunk fastest: a wavefront's transposed LDS writes land in
+        // distinct banks while its global reads stay 256-byte runs per k row
+        row = row0 + (idx / KQ) * 4;
+        k = (idx % KQ) * 4;
+        row = row < nrows ? row : nrows - 4;
+      }
+      if (!EXACT && idx >= NMB) row = 0;
+      int64_t o[1];
+      group_offsets<1>(grows, (uint32_t)row, o, 0);
+      kq[v] = k;
+      ptr[v] = base + o[0] + (int64_t)k * sk;
+    }
+  }
+
+  template <bool TAIL>
+  __device__ __forceinline__ void load(int k0) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const bool act = EXACT || tid + v * NT < NMB;
+      if constexpr (MODE == LOAD_KVEC) {
+        f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+        if (act && (!TAIL || k0 + kq[v] < K)) x = *reinterpret_cast<const f32x4_t*>(ptr[v]);
+        st[v] = x;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+          if (act && (!TAIL || k0 + kq[v] + j < K)) x = *reinterpret_cast<const f32x4_t*>(ptr[v] + j * sk);
+          st[4 * v + j] = x;
+        }
+      }
+      ptr[v] += BK * sk;
+    }
+  }
+
+  __device__ __forceinline__ void store(char* lds) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = tid + v * NT;
+      if (!EXACT && idx >= NMB) continue;
+      if constexpr (MODE == LOAD_KVEC) {
+        lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[v]);
+      } else {
+        const int r0 = (idx / KQ) * 4;
+        const int kc = (idx % KQ) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          f32x4_t t = {st[4 * v + 0][i], st[4 * v + 1][i], st[4 * v + 2][i], st[4 * v + 3][i]};
+          lds_put4<P, R, BK>(lds, r0 + i, kc, t);
         }
       }
     }
@@ -284,7 +391,9 @@ __device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int& tm, i
   tn = in_g / gsize;
 }
 
-template <int P, int BM, int BN, int BK, int WM, int WN>
+// AMODE / BMODE: LOAD_KVEC or LOAD_MNVEC select the fast gathers (single
+// merged K axis); -1 selects the run-time-mode gathers that handle any layout.
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE = -1, int BMODE = -1>
 struct GemmTile {
   static constexpr int NT = WM * WN * 64;
   static constexpr int TM = BM / WM / 32;
@@ -296,8 +405,23 @@ struct GemmTile {
   static_assert(TM >= 1 && TN >= 1, "tile too small for 32x32 blocks");
   static_assert(BK % 16 == 0, "BK must be a multiple of 16");
 
-  __device__ static __forceinline__ void compute(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN], int wm_off,
-                                        int wn_off) {
+  // stages summed into the temporary before it is added to the accumulator (64 k)
+  static constexpr int FLUSH = BK >= 64 ? 1 : 64 / BK;
+  static constexpr int TMT = PrecInfo<P>::planes > 1 ? TM : 1;
+  static constexpr int TNT = PrecInfo<P>::planes > 1 ? TN : 1;
+
+  __device__ static __forceinline__ void flush_tmp(f32x16_t (&acc)[TM][TN], f32x16_t (&tmp)[TMT][TNT]) {
+    if constexpr (PrecInfo<P>::planes > 1) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] += tmp[i][j];
+    }
+  }
+
+  __device__ static __forceinline__ void compute(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN],
+                                                 f32x16_t (&tmp)[TMT][TNT], bool first, bool flush, int wm_off,
+                                                 int wn_off) {
     const int lane = threadIdx.x & 63;
     const int lr = lane & 31, lh = lane >> 5;
     if constexpr (!PrecInfo<P>::bf) {
@@ -350,27 +474,24 @@ struct GemmTile {
             for (int j = 0; j < TN; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][0][i], bfr[kc][0][j], acc[i][j], 0, 0, 0);
       } else {
-        // The term products of this stage are summed by the matrix cores into a
-        // zero-based temporary, which is then added to the running accumulator
-        // with a round-to-nearest-even VALU add.  Repeated matrix-core
-        // accumulation onto a large running sum drifts (measured bias of about
-        // -1e-6 relative at K = 2048); a small temporary keeps that drift
-        // proportional to the temporary, not to the result.
+        // The term products are summed by the matrix cores into a temporary
+        // that starts from zero every FLUSH stages and is then added to the
+        // running accumulator with a round-to-nearest-even VALU add.
+        // Repeated matrix-core accumulation onto a large running sum drifts
+        // (measured bias of about -1e-6 relative at K = 2048); a small
+        // temporary keeps that drift proportional to the temporary.
         const f32x16_t zero = {};
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          f32x16_t tmp[TM];
+        for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-          for (int kc = 0; kc < NKC; ++kc)
+          for (int q = 0; q < PrecInfo<P>::nprod; ++q)
 #pragma unroll
-            for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
               for (int i = 0; i < TM; ++i)
-                tmp[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][prod_a(P, q)][i], bfr[kc][prod_b(P, q)][j],
-                                                                 (kc == 0 && q == 0) ? zero : tmp[i], 0, 0, 0);
-#pragma unroll
-          for (int i = 0; i < TM; ++i) acc[i][j] += tmp[i];
-        }
+                tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][prod_a(P, q)][i], bfr[kc][prod_b(P, q)][j],
+                                                                    (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
+        if (flush) flush_tmp(acc, tmp);
       }
     }
   }
@@ -387,11 +508,6 @@ struct GemmTile {
     float scale = 1.0f;
     if (d.a_scale_bits) scale = pow2_inverse_scale(d.a_scale_bits[bz]);
 
-    OperandLoader<P, BM, BK, NT, 0> la;
-    OperandLoader<P, BN, BK, NT, 1> lb;
-    la.init(d.a_mode, d.a + bz * d.a_bs, d.gm, m0, d.M, d.K, scale);
-    lb.init(d.b_mode, d.b + bz * d.b_bs, d.gn, n0, d.N, d.K, 1.0f);
-
     f32x16_t acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -399,27 +515,84 @@ struct GemmTile {
       for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    f32x16_t tmp[TMT][TNT];
 
     const int nk = (d.K + BK - 1) / BK;
-    la.load(0, gk_lds);
-    lb.load(0, gk_lds);
-    la.store(smem);
-    lb.store(smem + bytesA);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-      char* cur = smem + (kt & 1) * stage;
-      char* nxt = smem + ((kt + 1) & 1) * stage;
-      const bool more = kt + 1 < nk;
-      if (more) {
-        la.load((kt + 1) * BK, gk_lds);
-        lb.load((kt + 1) * BK, gk_lds);
-      }
-      compute(cur, cur + bytesA, acc, wm_off, wn_off);
-      if (more) {
-        la.store(nxt);
-        lb.store(nxt + bytesA);
-      }
+    if constexpr (AMODE < 0 || BMODE < 0) {
+      OperandLoader<P, BM, BK, NT, 0> la;
+      OperandLoader<P, BN, BK, NT, 1> lb;
+      la.init(d.a_mode, d.a + bz * d.a_bs, d.gm, m0, d.M, d.K, 1.0f);
+      lb.init(d.b_mode, d.b + bz * d.b_bs, d.gn, n0, d.N, d.K, 1.0f);
+      la.load(0, gk_lds);
+      lb.load(0, gk_lds);
+      la.store(smem);
+      lb.store(smem + bytesA);
       __syncthreads();
+      // stages in groups of FLUSH, unrolled so the temporary's first and last
+      // stage are known at compile time
+      for (int kt0 = 0; kt0 < nk; kt0 += FLUSH) {
+#pragma unroll
+        for (int s = 0; s < FLUSH; ++s) {
+          const int kt = kt0 + s;
+          if (kt < nk) {
+            char* cur = smem + (kt & 1) * stage;
+            char* nxt = smem + ((kt + 1) & 1) * stage;
+            const bool more = kt + 1 < nk;
+            if (more) {
+              la.load((kt + 1) * BK, gk_lds);
+              lb.load((kt + 1) * BK, gk_lds);
+            }
+            compute(cur, cur + bytesA, acc, tmp, s == 0, s == FLUSH - 1, wm_off, wn_off);
+            if (more) {
+              la.store(nxt);
+              lb.store(nxt + bytesA);
+            }
+            __syncthreads();
+          }
+        }
+      }
+      if (nk % FLUSH != 0) flush_tmp(acc, tmp);
+    } else {
+      FastLoader<P, BM, BK, NT, AMODE> la;
+      FastLoader<P, BN, BK, NT, BMODE> lb;
+      la.init(d.a + bz * d.a_bs, d.gm, m0, d.M, d.gk.s[0][0], d.K);
+      lb.init(d.b + bz * d.b_bs, d.gn, n0, d.N, d.gk.s[1][0], d.K);
+      const int nfull = d.K / BK;
+      if (nfull > 0) {
+        la.template load<false>(0);
+        lb.template load<false>(0);
+      } else {
+        la.template load<true>(0);
+        lb.template load<true>(0);
+      }
+      la.store(smem);
+      lb.store(smem + bytesA);
+      __syncthreads();
+      for (int kt0 = 0; kt0 < nk; kt0 += FLUSH) {
+#pragma unroll
+        for (int s = 0; s < FLUSH; ++s) {
+          const int kt = kt0 + s;
+          if (kt < nk) {
+            char* cur = smem + (kt & 1) * stage;
+            char* nxt = smem + ((kt + 1) & 1) * stage;
+            const bool more = kt + 1 < nk;
+            if (kt + 1 < nfull) {
+              la.template load<false>((kt + 1) * BK);
+              lb.template load<false>((kt + 1) * BK);
+            } else if (more) {
+              la.template load<true>((kt + 1) * BK);
+              lb.template load<true>((kt + 1) * BK);
+            }
+            compute(cur, cur + bytesA, acc, tmp, s == 0, s == FLUSH - 1, wm_off, wn_off);
+            if (more) {
+              la.store(nxt);
+              lb.store(nxt + bytesA);
+            }
+            __syncthreads();
+          }
+        }
+      }
+      if (nk % FLUSH != 0) flush_tmp(acc, tmp);
     }
 
     // epilogue.  The output offsets of the tile's BM rows and BN columns are
@@ -445,6 +618,8 @@ struct GemmTile {
     float* C = d.c + bz * d.c_bs;
     float amax = 0.f;
     const bool mvec = d.c_mode == STORE_MVEC;
+    // the operand rescale 2^-e (exact) is applied to the product instead of the A operand
+    const bool scaled = scale != 1.0f;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int nl = wn_off + 32 * j + lr;
@@ -455,7 +630,8 @@ struct GemmTile {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int ml = wm_off + 32 * i + 8 * q + 4 * lh;
-          const f32x4_t v = {acc[i][j][4 * q + 0], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+          f32x4_t v = {acc[i][j][4 * q + 0], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+          if (scaled) v *= scale;
           if (nok && m0 + ml < d.M) {
             if (mvec) {
               *reinterpret_cast<f32x4_t*>(C + offm[ml] + on) = v;

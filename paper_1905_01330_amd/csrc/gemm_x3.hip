@@ -2,6 +2,6 @@
 #include "gemm_inst.h"
 
 namespace tn {
-GemmFn gemm_fn_x3(int cfg) { return gemm_fn<P_X3>(cfg); }
+GemmFn gemm_fn_x3(int cfg, int variant) { return gemm_fn<P_X3>(cfg, variant); }
 GroupedFn grouped_fn_x3(int cfg) { return grouped_fn<P_X3>(cfg); }
 }  // namespace tn

@@ -2,6 +2,6 @@
 #include "gemm_inst.h"
 
 namespace tn {
-GemmFn gemm_fn_x6(int cfg) { return gemm_fn<P_X6>(cfg); }
+GemmFn gemm_fn_x6(int cfg, int variant) { return gemm_fn<P_X6>(cfg, variant); }
 GroupedFn grouped_fn_x6(int cfg) { return grouped_fn<P_X6>(cfg); }
 }  // namespace tn
