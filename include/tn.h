@@ -194,7 +194,11 @@ int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* logn
  * and stores one of every `ckpt_every` of them to ckpt (nullable; FP32,
  * layout documented by tn_mps_classifier_ckpt_shape) for the backward.
  * Backward: dlogits [B, n_labels] -> dsites (same shapes as sites); it
- * recomputes the vectors between checkpoints.  prec: FP32 or SPLIT_BF16.
+ * recomputes the vectors between checkpoints (ckpt is required there).
+ * prec: FP32 or SPLIT_BF16; it applies to the label-site and weight-gradient
+ * contractions, the chain steps themselves run on FP32 matrix cores.
+ * Requirements: 1 <= label_site <= n_sites - 2, chi <= 256, every site
+ * contiguous, 1 <= ckpt_every <= 64.
  * ------------------------------------------------------------------- */
 int32_t tn_mps_classifier_ckpt_shape(int32_t n_sites, int32_t label_site, int32_t batch,
                                      int32_t chi, int32_t ckpt_every, int64_t* n_floats);
@@ -210,6 +214,13 @@ int32_t tn_mps_classifier_backward(int32_t n_sites, int32_t label_site, int32_t 
                                    const float* ckpt, int32_t ckpt_every,
                                    const tn_tensor* dlogits, tn_tensor* dsites, void* workspace,
                                    size_t ws_bytes, int32_t prec, void* stream);
+
+/* Softmax cross-entropy of the scores against integer labels (the loss the
+ * classifier is trained with): loss (DEVICE double) = mean_b [logsumexp(f_b)
+ * - f_b[y_b]], dlogits[b, l] = (softmax(f_b)_l - [l == y_b]) / batch.
+ * labels: DEVICE int64 [batch].  workspace >= 8 * batch bytes. */
+int32_t tn_softmax_xent(const tn_tensor* logits, const int64_t* labels, int32_t batch, double* loss,
+                        tn_tensor* dlogits, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
  * Tile autotuner for the contraction GEMM.  level 0: heuristic tiles only;

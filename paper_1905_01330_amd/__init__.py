@@ -6,6 +6,8 @@ the library; the first call does, and fails loudly if it is not built.
 """
 from .api import (  # noqa: F401
     BatchedInner,
+    ClassifierFunction,
+    MPSClassifier,
     EnvSweep,
     contract_between,
     contract_network,
@@ -14,6 +16,7 @@ from .api import (  # noqa: F401
     mps_inner_batched,
     mps_left_canonicalize,
     outer_product,
+    softmax_xent,
     tensordot,
     trace_edge,
     tune_force_config,

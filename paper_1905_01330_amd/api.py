@@ -206,3 +206,81 @@ def tune_last_choice() -> int:
 
 def tune_num_configs() -> int:
     return int(L.lib().tn_tune_num_configs())
+
+
+# ---------------------------------------------------------------------------
+# MPS classifier (section IV.A)
+
+
+class MPSClassifier:
+    """Prepared classifier evaluation: workspace and checkpoints allocated once.
+
+    sites: list of contiguous float32 device tensors [D_k, 2, D_{k+1}] with the
+    label site [chi, 2, n_labels, chi]; pixels [B, N] in [0, 1].
+    """
+
+    def __init__(self, n_sites, label_site, n_labels, chi, batch, ckpt_every=28, prec="fp32", device="cuda:0"):
+        self.n, self.c, self.L, self.chi, self.B, self.E = n_sites, label_site, n_labels, chi, batch, ckpt_every
+        self.prec = L.prec_code(prec)
+        nb = C.c_size_t(0)
+        L.check(L.lib().tn_mps_classifier_workspace(n_sites, label_site, n_labels, batch, chi, ckpt_every, C.byref(nb)))
+        self.nbytes = nb.value
+        self.ws = _workspace(self.nbytes, device)
+        nf = C.c_int64(0)
+        L.check(L.lib().tn_mps_classifier_ckpt_shape(n_sites, label_site, batch, chi, ckpt_every, C.byref(nf)))
+        self.ckpt = torch.empty(max(nf.value, 1), dtype=torch.float32, device=device)
+
+    def forward(self, sites, pixels, logits=None):
+        if logits is None:
+            logits = torch.empty((self.B, self.L), dtype=torch.float32, device=pixels.device)
+        ds, dp, dl = L.tensor_array(sites), L.tensor_desc(pixels), L.tensor_desc(logits)
+        L.check(L.lib().tn_mps_classifier_forward(self.n, self.c, self.L, ds, C.byref(dp), C.byref(dl),
+                                                  C.c_void_p(self.ckpt.data_ptr()), self.E,
+                                                  C.c_void_p(self.ws.data_ptr()), self.nbytes, self.prec,
+                                                  L.stream_ptr()))
+        return logits
+
+    def backward(self, sites, pixels, dlogits, dsites=None):
+        if dsites is None:
+            dsites = [torch.empty_like(s) for s in sites]
+        ds, dp, dg, dd = L.tensor_array(sites), L.tensor_desc(pixels), L.tensor_desc(dlogits), L.tensor_array(dsites)
+        L.check(L.lib().tn_mps_classifier_backward(self.n, self.c, self.L, ds, C.byref(dp),
+                                                   C.c_void_p(self.ckpt.data_ptr()), self.E, C.byref(dg), dd,
+                                                   C.c_void_p(self.ws.data_ptr()), self.nbytes, self.prec,
+                                                   L.stream_ptr()))
+        return dsites
+
+
+def softmax_xent(logits, labels):
+    """Batch-mean softmax cross-entropy and its gradient with respect to the logits."""
+    B = logits.shape[0]
+    loss = torch.empty(1, dtype=torch.float64, device=logits.device)
+    dlogits = torch.empty_like(logits)
+    ws = _workspace(8 * B, logits.device)
+    dl, dd = L.tensor_desc(logits), L.tensor_desc(dlogits)
+    L.check(L.lib().tn_softmax_xent(C.byref(dl), C.c_void_p(labels.data_ptr()), B, C.c_void_p(loss.data_ptr()),
+                                    C.byref(dd), C.c_void_p(ws.data_ptr()), 8 * B, L.stream_ptr()))
+    return loss, dlogits
+
+
+class ClassifierFunction(torch.autograd.Function):
+    """logits = f(sites; pixels) with the library's adjoint as the backward.
+
+    Use as ClassifierFunction.apply(model, pixels, *sites) where model is an
+    MPSClassifier sized for the batch; the forward keeps the checkpoints the
+    backward recomputes from.
+    """
+
+    @staticmethod
+    def forward(ctx, model, pixels, *sites):
+        sites = [s.contiguous() for s in sites]
+        logits = model.forward(sites, pixels)
+        ctx.model = model
+        ctx.save_for_backward(pixels, *sites)
+        return logits
+
+    @staticmethod
+    def backward(ctx, dlogits):
+        pixels, *sites = ctx.saved_tensors
+        dsites = ctx.model.backward(sites, pixels, dlogits.contiguous())
+        return (None, None, *dsites)

@@ -24,6 +24,9 @@ tn_tensor contiguous_view(void* data, int32_t dtype, int32_t rank, const int64_t
 // are merged; each group is ordered so its most contiguous axis is inner.
 int32_t plan_gemm(const tn_tensor& a, const tn_tensor& b, int32_t n_pairs, const int32_t* axes_a,
                   const int32_t* axes_b, const tn_tensor& out, GemmDesc& d);
+// (re)select the operand load and store modes after a descriptor's pointers
+// or batch strides change
+void choose_modes(GemmDesc& d);
 
 // reductions: out[r] = sum_k x * y (y may be null)
 struct AxisSpec {
