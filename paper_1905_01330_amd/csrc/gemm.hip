@@ -23,7 +23,8 @@ struct Cfg {
 static const Cfg kCfgs[] = {
     {256, 128, 16, 2, 2, 0.75f}, {128, 256, 16, 2, 2, 0.80f}, {128, 128, 16, 2, 2, 1.00f},
     {128, 128, 32, 2, 2, 0.95f}, {128, 64, 32, 2, 2, 0.70f},  {64, 128, 32, 2, 2, 0.70f},
-    {64, 64, 32, 2, 2, 0.55f},   {32, 32, 32, 1, 1, 0.25f},
+    {64, 64, 32, 2, 2, 0.55f},   {32, 32, 32, 1, 1, 0.25f},  {160, 128, 16, 1, 4, 1.00f},
+    {128, 160, 16, 4, 1, 1.00f},
 };
 static constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 

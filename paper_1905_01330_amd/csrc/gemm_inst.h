@@ -7,8 +7,24 @@
 
 namespace tn {
 
+// Waves per SIMD to hold the register budget to: what the LDS footprint
+// allows (160 KB per CU, four SIMDs), capped at 2, and 1 when a wave's
+// accumulators (plus the split precisions' temporaries) exceed 128 registers,
+// where a smaller budget would only spill.
 template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE, int BMODE>
-__global__ void __launch_bounds__(WM* WN * 64) gemm_kernel(const GemmDesc d) {
+constexpr int lds_waves_per_simd() {
+  using T = GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>;
+  constexpr int wg = (160 * 1024) / T::lds_bytes;
+  constexpr int w = wg * WM * WN / 4;
+  constexpr int acc_regs = T::TM * T::TN * 16 * (PrecInfo<P>::planes > 1 ? 2 : 1);
+  if (acc_regs > 128) return 1;
+  return w < 1 ? 1 : (w > 2 ? 2 : w);
+}
+
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE, int BMODE>
+__global__ void __launch_bounds__(WM* WN * 64)
+    __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd<P, BM, BN, BK, WM, WN, AMODE, BMODE>())))
+        gemm_kernel(const GemmDesc d) {
   __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::lds_bytes];
   __shared__ Group gk;
   if constexpr (AMODE < 0 || BMODE < 0) {
@@ -90,6 +106,8 @@ GemmFn gemm_fn_modes(int cfg) {
     case 4: return gemm_kernel<P, 128, 64, 32, 2, 2, AM, BM_>;
     case 5: return gemm_kernel<P, 64, 128, 32, 2, 2, AM, BM_>;
     case 6: return gemm_kernel<P, 64, 64, 32, 2, 2, AM, BM_>;
+    case 8: return gemm_kernel<P, 160, 128, 16, 1, 4, AM, BM_>;
+    case 9: return gemm_kernel<P, 128, 160, 16, 4, 1, AM, BM_>;
     default: return gemm_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }

@@ -54,9 +54,40 @@ __device__ inline float pow2_inverse_scale(uint32_t bits) {
 template <int P, int R, int BK>
 struct LdsOperand {
   static constexpr int LDK = BK + 4;   // fp32 row pitch (floats)
-  static constexpr int LDH = BK + 8;   // bf16 row pitch (elements)
+  static constexpr int LDH = BK;       // bf16 row pitch (elements): unpadded, see bf16_slot
   static constexpr int bytes = PrecInfo<P>::bf ? R * LDH * 2 * PrecInfo<P>::planes : R * LDK * 4;
 };
+
+// Element offset of (row, k) in an unpadded BF16 plane with BK elements per
+// row.  The plane is cut into 16-row groups; row r = 16q + 4a + m of a group
+// is placed in a permuted row slot and its 16-byte chunks (8 k each) are
+// XOR-swizzled, so that every access pattern of the kernel needs only the
+// minimum number of sweeps over the 64 LDS banks:
+//   - MFMA fragment reads: 16 consecutive rows, one chunk each;
+//   - k-contiguous gathers: consecutive rows, 4 k per lane;
+//   - transposed gathers: rows 4g + i (g across the wavefront), 2 or 4 k.
+// The bank window of a row (BK/2 dwords; 128/BK windows per sweep) is
+// slot % (128/BK); the table below keeps it distinct across each pattern.
+template <int BK>
+__device__ __forceinline__ int bf16_slot(int row, int k) {
+  const int q = row >> 4, a = (row >> 2) & 3, m = row & 3;
+  int slot, sw;
+  if constexpr (BK == 16) {         // 8 windows, 2 chunks per row
+    const int win = (4 * q + a + 4 * (m >> 1)) & 7;
+    slot = 16 * q + 8 * (m & 1) + win;
+    sw = m & 1;
+  } else if constexpr (BK == 32) {  // 4 windows, 4 chunks per row
+    const int win = (a + m) & 3;
+    slot = 16 * q + 4 * m + win;
+    sw = m;
+  } else {                          // BK == 64: 2 windows, 8 chunks per row
+    static_assert(BK == 64, "BF16 LDS layout is defined for BK = 16, 32, 64");
+    const int win = (a + m) & 1;
+    slot = 16 * q + 2 * (4 * (a >> 1) + m) + win;
+    sw = 4 * (a >> 1) + m;
+  }
+  return slot * BK + ((((k >> 3) ^ sw)) << 3) + (k & 7);
+}
 
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -90,9 +121,8 @@ __device__ inline void lds_put4(char* base, int row, int kcol, f32x4_t v) {
     *reinterpret_cast<f32x4_t*>(p + row * LdsOperand<P, R, BK>::LDK + kcol) = v;
   } else {
     constexpr int NPL = PrecInfo<P>::planes;
-    constexpr int LDH = LdsOperand<P, R, BK>::LDH;
-    constexpr int plane = R * LDH;
-    __bf16* h = reinterpret_cast<__bf16*>(base) + row * LDH + kcol;
+    constexpr int plane = R * LdsOperand<P, R, BK>::LDH;
+    __bf16* h = reinterpret_cast<__bf16*>(base) + bf16_slot<BK>(row, kcol);
     uint32_t lo[3], hi[3];
     split_pair<NPL>(v[0], v[1], lo);
     split_pair<NPL>(v[2], v[3], hi);
@@ -101,6 +131,24 @@ __device__ inline void lds_put4(char* base, int row, int kcol, f32x4_t v) {
       u32x2_t w = {lo[p], hi[p]};
       *reinterpret_cast<u32x2_t*>(h + p * plane) = w;
     }
+  }
+}
+
+// Two consecutive k of one row (the 4 x 2 transposed micro-block)
+template <int P, int R, int BK>
+__device__ inline void lds_put2(char* base, int row, int kcol, float v0, float v1) {
+  if constexpr (!PrecInfo<P>::bf) {
+    float* p = reinterpret_cast<float*>(base);
+    f32x2_t w = {v0, v1};
+    *reinterpret_cast<f32x2_t*>(p + row * LdsOperand<P, R, BK>::LDK + kcol) = w;
+  } else {
+    constexpr int NPL = PrecInfo<P>::planes;
+    constexpr int plane = R * LdsOperand<P, R, BK>::LDH;
+    __bf16* h = reinterpret_cast<__bf16*>(base) + bf16_slot<BK>(row, kcol);
+    uint32_t t[3];
+    split_pair<NPL>(v0, v1, t);
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) *reinterpret_cast<uint32_t*>(h + p * plane) = t[p];
   }
 }
 
@@ -270,13 +318,17 @@ struct OperandLoader {
 //                      transposed in registers before the LDS store
 template <int P, int R, int BK, int NT, int MODE>
 struct FastLoader {
-  static constexpr int KQ = BK / 4;
-  static constexpr int NMB = MODE == LOAD_KVEC ? R * BK / 4 : R * BK / 16;
+  // m/n-contiguous operands are read as 4 rows x KD k micro-blocks (KD float4
+  // loads, transposed in registers).  KD = 4 when the 4 x 4 blocks cover the
+  // workgroup evenly, else KD = 2 so that no thread idles.
+  static constexpr int KD = (MODE == LOAD_KVEC || (R * BK / 16) % NT == 0 || (R * BK / 8) % NT != 0) ? 4 : 2;
+  static constexpr int KQ = MODE == LOAD_KVEC ? BK / 4 : BK / KD;
+  static constexpr int NMB = MODE == LOAD_KVEC ? R * BK / 4 : R * BK / (4 * KD);
   static constexpr int NV = (NMB + NT - 1) / NT;
   static constexpr bool EXACT = NMB % NT == 0;
-  static constexpr int NREG = MODE == LOAD_KVEC ? NV : 4 * NV;
+  static constexpr int NREG = MODE == LOAD_KVEC ? NV : KD * NV;
 
-  f32x4_t st[NREG];
+  f32x4_t st[2][NREG];   // two stages in flight (set = stage parity)
   const float* ptr[NV];
   int kq[NV];
   int64_t sk;
@@ -286,9 +338,10 @@ struct FastLoader {
     sk = sk_;
     K = K_;
     const int tid = threadIdx.x;
+    (void)tid;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int idx = tid + v * NT;
+      const int idx = block_of(v);
       int row, k;
       if constexpr (MODE == LOAD_KVEC) {
         row = row0 + idx / KQ;
@@ -296,12 +349,11 @@ struct FastLoader {
         row = row < nrows ? row : nrows - 1;
       } else {
         // k-chunk fastest: a wavefront's transposed LDS writes land in
-        // distinct banks while its global reads stay 256-byte runs per k row
+        // distinct banks while its global reads stay 128-byte runs per k row
         row = row0 + (idx / KQ) * 4;
-        k = (idx % KQ) * 4;
+        k = (idx % KQ) * KD;
         row = row < nrows ? row : nrows - 4;
       }
-      if (!EXACT && idx >= NMB) row = 0;
       int64_t o[1];
       group_offsets<1>(grows, (uint32_t)row, o, 0);
       kq[v] = k;
@@ -309,43 +361,61 @@ struct FastLoader {
     }
   }
 
-  template <bool TAIL>
+  // slot v of a thread covers micro-block idx; past the last block it repeats
+  // block idx % NMB (the same load and the same LDS store of the same value
+  // as another slot), which keeps the stage free of branches
+  __device__ static __forceinline__ int block_of(int v) {
+    const int idx = threadIdx.x + v * NT;
+    return (EXACT || idx < NMB) ? idx : idx % NMB;
+  }
+
+  template <bool TAIL, int SET>
   __device__ __forceinline__ void load(int k0) {
-    const int tid = threadIdx.x;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const bool act = EXACT || tid + v * NT < NMB;
       if constexpr (MODE == LOAD_KVEC) {
         f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-        if (act && (!TAIL || k0 + kq[v] < K)) x = *reinterpret_cast<const f32x4_t*>(ptr[v]);
-        st[v] = x;
+        if (!TAIL || k0 + kq[v] < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v]);
+        st[SET][v] = x;
       } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < KD; ++j) {
           f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-          if (act && (!TAIL || k0 + kq[v] + j < K)) x = *reinterpret_cast<const f32x4_t*>(ptr[v] + j * sk);
-          st[4 * v + j] = x;
+          if (!TAIL || k0 + kq[v] + j < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v] + j * sk);
+          st[SET][KD * v + j] = x;
         }
       }
       ptr[v] += BK * sk;
     }
   }
 
+  // load stage kt (k0 = kt * BK) into register set SET, if the stage exists
+  template <int SET>
+  __device__ __forceinline__ void load_stage(int kt, int nfull, int nk) {
+    if (kt < nfull)
+      load<false, SET>(kt * BK);
+    else if (kt < nk)
+      load<true, SET>(kt * BK);
+  }
+
+  template <int SET>
   __device__ __forceinline__ void store(char* lds) {
-    const int tid = threadIdx.x;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int idx = tid + v * NT;
-      if (!EXACT && idx >= NMB) continue;
+      const int idx = block_of(v);
       if constexpr (MODE == LOAD_KVEC) {
-        lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[v]);
+        lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[SET][v]);
       } else {
         const int r0 = (idx / KQ) * 4;
-        const int kc = (idx % KQ) * 4;
+        const int kc = (idx % KQ) * KD;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          f32x4_t t = {st[4 * v + 0][i], st[4 * v + 1][i], st[4 * v + 2][i], st[4 * v + 3][i]};
-          lds_put4<P, R, BK>(lds, r0 + i, kc, t);
+          if constexpr (KD == 4) {
+            f32x4_t t = {st[SET][4 * v + 0][i], st[SET][4 * v + 1][i], st[SET][4 * v + 2][i], st[SET][4 * v + 3][i]};
+            lds_put4<P, R, BK>(lds, r0 + i, kc, t);
+          } else {
+            lds_put2<P, R, BK>(lds, r0 + i, kc, st[SET][2 * v + 0][i], st[SET][2 * v + 1][i]);
+          }
         }
       }
     }
@@ -419,9 +489,16 @@ struct GemmTile {
     }
   }
 
+  // One stage: read the operand fragments from LDS, run `between` (work
+  // independent of this stage, e.g. the next stage's LDS stores, so the
+  // scheduler can interleave it with the matrix-core ops), then the MFMAs.
+  struct Nothing {
+    __device__ __forceinline__ void operator()() const {}
+  };
+  template <typename F = Nothing>
   __device__ static __forceinline__ void compute(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN],
                                                  f32x16_t (&tmp)[TMT][TNT], bool first, bool flush, int wm_off,
-                                                 int wn_off) {
+                                                 int wn_off, const F& between = F()) {
     const int lane = threadIdx.x & 63;
     const int lr = lane & 31, lh = lane >> 5;
     if constexpr (!PrecInfo<P>::bf) {
@@ -438,6 +515,7 @@ struct GemmTile {
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           bfr[j] = *reinterpret_cast<const f32x4_t*>(B + (wn_off + 32 * j + lr) * LDB + kc * 8 + lh * 4);
+        if (kc == 0) between();
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -453,26 +531,29 @@ struct GemmTile {
       const __bf16* A = reinterpret_cast<const __bf16*>(sa);
       const __bf16* B = reinterpret_cast<const __bf16*>(sb);
       constexpr int NKC = BK / 16;
-      bf16x8_t af[NKC][NPL][TM], bfr[NKC][NPL][TN];
-#pragma unroll
-      for (int kc = 0; kc < NKC; ++kc)
-#pragma unroll
-        for (int p = 0; p < NPL; ++p) {
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-            af[kc][p][i] = *reinterpret_cast<const bf16x8_t*>(A + p * BM * LDA + (wm_off + 32 * i + lr) * LDA + kc * 16 + lh * 8);
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            bfr[kc][p][j] = *reinterpret_cast<const bf16x8_t*>(B + p * BN * LDB + (wn_off + 32 * j + lr) * LDB + kc * 16 + lh * 8);
-        }
+      auto fa = [&](int kc, int p, int i) {
+        return *reinterpret_cast<const bf16x8_t*>(A + p * BM * LDA + bf16_slot<BK>(wm_off + 32 * i + lr, kc * 16 + lh * 8));
+      };
+      auto fb = [&](int kc, int p, int j) {
+        return *reinterpret_cast<const bf16x8_t*>(B + p * BN * LDB + bf16_slot<BK>(wn_off + 32 * j + lr, kc * 16 + lh * 8));
+      };
       if constexpr (P == P_BF16) {
+        bf16x8_t af[NKC][TM], bfr[NKC][TN];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i) af[kc][i] = fa(kc, 0, i);
+#pragma unroll
+          for (int j = 0; j < TN; ++j) bfr[kc][j] = fb(kc, 0, j);
+        }
+        between();
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
           for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][0][i], bfr[kc][0][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][i], bfr[kc][j], acc[i][j], 0, 0, 0);
       } else {
         // The term products are summed by the matrix cores into a temporary
         // that starts from zero every FLUSH stages and is then added to the
@@ -480,17 +561,69 @@ struct GemmTile {
         // Repeated matrix-core accumulation onto a large running sum drifts
         // (measured bias of about -1e-6 relative at K = 2048); a small
         // temporary keeps that drift proportional to the temporary.
+        // The fragments of the narrower side stay resident; the other side's
+        // term planes are read one 32-wide block at a time.
         const f32x16_t zero = {};
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc)
+        for (int kc = 0; kc < NKC; ++kc) {
+          if constexpr (TM * TN <= 4) {
+            bf16x8_t af[NPL][TM], bfr[NPL][TN];
 #pragma unroll
-          for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+            for (int p = 0; p < NPL; ++p) {
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
+              for (int i = 0; i < TM; ++i) af[p][i] = fa(kc, p, i);
 #pragma unroll
-              for (int i = 0; i < TM; ++i)
-                tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][prod_a(P, q)][i], bfr[kc][prod_b(P, q)][j],
-                                                                    (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
+              for (int j = 0; j < TN; ++j) bfr[p][j] = fb(kc, p, j);
+            }
+            if (kc == 0) between();
+#pragma unroll
+            for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+#pragma unroll
+              for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                  tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)][i], bfr[prod_b(P, q)][j],
+                                                                      (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
+          } else if constexpr (TM >= TN) {
+            bf16x8_t bfr[NPL][TN];
+#pragma unroll
+            for (int p = 0; p < NPL; ++p)
+#pragma unroll
+              for (int j = 0; j < TN; ++j) bfr[p][j] = fb(kc, p, j);
+            if (kc == 0) between();
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+              bf16x8_t af[NPL];
+#pragma unroll
+              for (int p = 0; p < NPL; ++p) af[p] = fa(kc, p, i);
+#pragma unroll
+              for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                  tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)], bfr[prod_b(P, q)][j],
+                                                                      (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
+            }
+          } else {
+            bf16x8_t af[NPL][TM];
+#pragma unroll
+            for (int p = 0; p < NPL; ++p)
+#pragma unroll
+              for (int i = 0; i < TM; ++i) af[p][i] = fa(kc, p, i);
+            if (kc == 0) between();
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              bf16x8_t bfr[NPL];
+#pragma unroll
+              for (int p = 0; p < NPL; ++p) bfr[p] = fb(kc, p, j);
+#pragma unroll
+              for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                  tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)][i], bfr[prod_b(P, q)],
+                                                                      (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
+            }
+          }
+        }
         if (flush) flush_tmp(acc, tmp);
       }
     }
@@ -558,35 +691,80 @@ struct GemmTile {
       la.init(d.a + bz * d.a_bs, d.gm, m0, d.M, d.gk.s[0][0], d.K);
       lb.init(d.b + bz * d.b_bs, d.gn, n0, d.N, d.gk.s[1][0], d.K);
       const int nfull = d.K / BK;
-      if (nfull > 0) {
-        la.template load<false>(0);
-        lb.template load<false>(0);
-      } else {
-        la.template load<true>(0);
-        lb.template load<true>(0);
-      }
-      la.store(smem);
-      lb.store(smem + bytesA);
+      // Software pipeline: global loads run two stages ahead in two register
+      // sets (set = stage parity); while stage kt's MFMAs run, stage kt+1 is
+      // split and stored into the other LDS buffer.  One barrier per stage.
+      la.template load_stage<0>(0, nfull, nk);
+      lb.template load_stage<0>(0, nfull, nk);
+      la.template load_stage<1>(1, nfull, nk);
+      lb.template load_stage<1>(1, nfull, nk);
+      la.template store<0>(smem);
+      lb.template store<0>(smem + bytesA);
       __syncthreads();
-      for (int kt0 = 0; kt0 < nk; kt0 += FLUSH) {
+      static_assert(FLUSH % 2 == 0 || FLUSH == 1, "stage groups must keep the register-set parity static");
+      constexpr int G = FLUSH == 1 ? 2 : FLUSH;   // stages per unrolled group (even)
+      int kt0 = 0;
+      // steady state: every stage of the group loads a full stage two ahead
+      // and stores the next one, so a stage is one straight-line block that
+      // the scheduler can interleave (loads, split, LDS traffic and MFMAs)
+      for (; kt0 + G + 1 < nfull; kt0 += G) {
 #pragma unroll
-        for (int s = 0; s < FLUSH; ++s) {
+        for (int s = 0; s < G; ++s) {
+          const int kt = kt0 + s;
+          char* cur = smem + (s & 1) * stage;
+          char* nxt = smem + ((s + 1) & 1) * stage;
+          const bool first = FLUSH == 1 ? true : s == 0;
+          const bool flush = FLUSH == 1 ? true : s == FLUSH - 1;
+          if (s & 1) {
+            la.template load<false, 1>((kt + 2) * BK);
+            lb.template load<false, 1>((kt + 2) * BK);
+            auto st_next = [&]() {
+              la.template store<0>(nxt);
+              lb.template store<0>(nxt + bytesA);
+            };
+            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+          } else {
+            la.template load<false, 0>((kt + 2) * BK);
+            lb.template load<false, 0>((kt + 2) * BK);
+            auto st_next = [&]() {
+              la.template store<1>(nxt);
+              lb.template store<1>(nxt + bytesA);
+            };
+            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+          }
+          __syncthreads();
+        }
+      }
+      // the last groups: loads may be partial or absent
+      for (; kt0 < nk; kt0 += G) {
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
           const int kt = kt0 + s;
           if (kt < nk) {
-            char* cur = smem + (kt & 1) * stage;
-            char* nxt = smem + ((kt + 1) & 1) * stage;
-            const bool more = kt + 1 < nk;
-            if (kt + 1 < nfull) {
-              la.template load<false>((kt + 1) * BK);
-              lb.template load<false>((kt + 1) * BK);
-            } else if (more) {
-              la.template load<true>((kt + 1) * BK);
-              lb.template load<true>((kt + 1) * BK);
-            }
-            compute(cur, cur + bytesA, acc, tmp, s == 0, s == FLUSH - 1, wm_off, wn_off);
-            if (more) {
-              la.store(nxt);
-              lb.store(nxt + bytesA);
+            char* cur = smem + (s & 1) * stage;
+            char* nxt = smem + ((s + 1) & 1) * stage;
+            const bool first = FLUSH == 1 ? true : s == 0;
+            const bool flush = FLUSH == 1 ? true : s == FLUSH - 1;
+            if (s & 1) {
+              la.template load_stage<1>(kt + 2, nfull, nk);
+              lb.template load_stage<1>(kt + 2, nfull, nk);
+              auto st_next = [&]() {
+                if (kt + 1 < nk) {
+                  la.template store<0>(nxt);
+                  lb.template store<0>(nxt + bytesA);
+                }
+              };
+              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+            } else {
+              la.template load_stage<0>(kt + 2, nfull, nk);
+              lb.template load_stage<0>(kt + 2, nfull, nk);
+              auto st_next = [&]() {
+                if (kt + 1 < nk) {
+                  la.template store<1>(nxt);
+                  lb.template store<1>(nxt + bytesA);
+                }
+              };
+              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
             }
             __syncthreads();
           }
