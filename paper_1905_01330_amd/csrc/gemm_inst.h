@@ -16,7 +16,8 @@ constexpr int lds_waves_per_simd() {
   using T = GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>;
   constexpr int wg = (160 * 1024) / T::lds_bytes;
   constexpr int w = wg * WM * WN / 4;
-  constexpr int acc_regs = T::TM * T::TN * 16 * (PrecInfo<P>::planes > 1 ? 2 : 1);
+  constexpr int acc_regs = T::TM * T::TN * 16 + T::TMT * T::TNT * 16 * (PrecInfo<P>::planes > 1 ? 1 : 0) +
+                           (T::CHAIN ? 32 : 0);
   if (acc_regs > 128) return 1;
   return w < 1 ? 1 : (w > 2 ? 2 : w);
 }
