@@ -168,6 +168,139 @@ __global__ void __launch_bounds__(256) wstep_right_kernel(const float* __restric
   }
 }
 
+// Specialised MPO steps for operator bonds WL, WR <= 5 and d = 2: one grid row
+// per a (no index division), four consecutive b per thread (16-byte loads and
+// stores), operand vectors held in registers.  Same FP64 accumulation.
+typedef float f32x4w_t __attribute__((ext_vector_type(4)));
+
+template <int WL, int WR, int D>
+__global__ void __launch_bounds__(256) wstep_left_fixed(const float* __restrict__ t1, float* __restrict__ t2,
+                                                        const float* __restrict__ w, int64_t w0, int64_t w1,
+                                                        int64_t w2, int64_t w3, int db) {
+  __shared__ float sw[WL * WR * D * D];
+  for (int i = threadIdx.x; i < WL * WR * D * D; i += blockDim.x) {
+    const int s = i % D, t = (i / D) % D, v = (i / (D * D)) % WR, u = i / (D * D * WR);
+    sw[i] = w[u * w0 + v * w1 + t * w2 + s * w3];
+  }
+  __syncthreads();
+  const int64_t a = blockIdx.y;
+  const int b = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (b >= db) return;
+  f32x4w_t x[WL][D];
+#pragma unroll
+  for (int u = 0; u < WL; ++u)
+#pragma unroll
+    for (int s = 0; s < D; ++s) x[u][s] = *reinterpret_cast<const f32x4w_t*>(t1 + ((a * WL + u) * D + s) * db + b);
+#pragma unroll
+  for (int t = 0; t < D; ++t)
+#pragma unroll
+    for (int v = 0; v < WR; ++v) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < WL; ++u)
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          const double c = sw[((u * WR + v) * D + t) * D + s];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] += c * (double)x[u][s][e];
+        }
+      f32x4w_t o = {(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
+      *reinterpret_cast<f32x4w_t*>(t2 + ((a * D + t) * WR + v) * db + b) = o;
+    }
+}
+
+template <int WL, int WR, int D>
+__global__ void __launch_bounds__(256) wstep_right_fixed(const float* __restrict__ t1, float* __restrict__ t2,
+                                                         const float* __restrict__ w, int64_t w0, int64_t w1,
+                                                         int64_t w2, int64_t w3, int da, int db) {
+  __shared__ float sw[WL * WR * D * D];
+  for (int i = threadIdx.x; i < WL * WR * D * D; i += blockDim.x) {
+    const int s = i % D, t = (i / D) % D, v = (i / (D * D)) % WR, u = i / (D * D * WR);
+    sw[i] = w[u * w0 + v * w1 + t * w2 + s * w3];
+  }
+  __syncthreads();
+  const int64_t a = blockIdx.y;
+  const int b = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (b >= db) return;
+  // x[s][e * WR + v] = T1'[a, s, b + e, v]: 4 * WR consecutive floats per s
+  float x[D][4 * WR];
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    const float* src = t1 + ((a * D + s) * db + b) * WR;
+#pragma unroll
+    for (int q = 0; q < WR; ++q) {
+      const f32x4w_t y = *reinterpret_cast<const f32x4w_t*>(src + 4 * q);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[s][4 * q + e] = y[e];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < WL; ++u)
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < D; ++s)
+#pragma unroll
+        for (int v = 0; v < WR; ++v) {
+          const double c = sw[((u * WR + v) * D + t) * D + s];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] += c * (double)x[s][e * WR + v];
+        }
+      f32x4w_t o = {(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
+      *reinterpret_cast<f32x4w_t*>(t2 + ((u * (int64_t)da + a) * D + t) * db + b) = o;
+    }
+}
+
+typedef void (*WstepLeftFn)(const float*, float*, const float*, int64_t, int64_t, int64_t, int64_t, int);
+typedef void (*WstepRightFn)(const float*, float*, const float*, int64_t, int64_t, int64_t, int64_t, int, int);
+
+template <int WL>
+static WstepLeftFn wl_pick(int wr) {
+  switch (wr) {
+    case 1: return wstep_left_fixed<WL, 1, 2>;
+    case 2: return wstep_left_fixed<WL, 2, 2>;
+    case 3: return wstep_left_fixed<WL, 3, 2>;
+    case 4: return wstep_left_fixed<WL, 4, 2>;
+    case 5: return wstep_left_fixed<WL, 5, 2>;
+    default: return nullptr;
+  }
+}
+template <int WL>
+static WstepRightFn wr_pick(int wr) {
+  switch (wr) {
+    case 1: return wstep_right_fixed<WL, 1, 2>;
+    case 2: return wstep_right_fixed<WL, 2, 2>;
+    case 3: return wstep_right_fixed<WL, 3, 2>;
+    case 4: return wstep_right_fixed<WL, 4, 2>;
+    case 5: return wstep_right_fixed<WL, 5, 2>;
+    default: return nullptr;
+  }
+}
+// the specialised step for (wl, wr, d), or NULL when the shape needs the generic kernel
+static WstepLeftFn wstep_left_fn(int wl, int wr, int d, int64_t db, const void* t1, const void* t2) {
+  if (d != 2 || db % 4 || reinterpret_cast<uintptr_t>(t1) % 16 || reinterpret_cast<uintptr_t>(t2) % 16) return nullptr;
+  switch (wl) {
+    case 1: return wl_pick<1>(wr);
+    case 2: return wl_pick<2>(wr);
+    case 3: return wl_pick<3>(wr);
+    case 4: return wl_pick<4>(wr);
+    case 5: return wl_pick<5>(wr);
+    default: return nullptr;
+  }
+}
+static WstepRightFn wstep_right_fn(int wl, int wr, int d, int64_t db, const void* t1, const void* t2) {
+  if (d != 2 || db % 4 || reinterpret_cast<uintptr_t>(t1) % 16 || reinterpret_cast<uintptr_t>(t2) % 16) return nullptr;
+  switch (wl) {
+    case 1: return wr_pick<1>(wr);
+    case 2: return wr_pick<2>(wr);
+    case 3: return wr_pick<3>(wr);
+    case 4: return wr_pick<4>(wr);
+    case 5: return wr_pick<5>(wr);
+    default: return nullptr;
+  }
+}
+
 __global__ void fill_one_kernel(float* p) { p[0] = 1.0f; }
 
 __global__ void energy_kernel(const float* l_last, const float* r_first, double* e2) {
@@ -343,9 +476,13 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
       TN_TRY(plan_gemm(cur, psi[k], 1, a1, b1, T1, g));
       TN_TRY(launch_gemm(g, prec, st));
       const tn_tensor& W = mpo[k];
-      hipLaunchKernelGGL(wstep_left_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
-                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
-                         (int)db, (int)wl, (int)wr, (int)d);
+      if (WstepLeftFn f = wstep_left_fn((int)wl, (int)wr, (int)d, db, t1, t2))
+        hipLaunchKernelGGL(f, dim3((unsigned)((db / 4 + 255) / 256), (unsigned)da), dim3(256), 0, st, t1, t2,
+                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)db);
+      else
+        hipLaunchKernelGGL(wstep_left_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
+                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                           (int)db, (int)wl, (int)wr, (int)d);
       TN_TRY(hip_check(hipGetLastError(), "wstep left"));
       const int32_t a3[2] = {0, 1}, b3[2] = {0, 1};
       TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
@@ -367,9 +504,14 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
       TN_TRY(plan_gemm(psi[k], cur, 1, a1, b1, T1, g));
       TN_TRY(launch_gemm(g, prec, st));
       const tn_tensor& W = mpo[k];
-      hipLaunchKernelGGL(wstep_right_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
-                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
-                         (int)db, (int)wl, (int)wr, (int)d);
+      if (WstepRightFn f = wstep_right_fn((int)wl, (int)wr, (int)d, db, t1, t2))
+        hipLaunchKernelGGL(f, dim3((unsigned)((db / 4 + 255) / 256), (unsigned)da), dim3(256), 0, st, t1, t2,
+                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                           (int)db);
+      else
+        hipLaunchKernelGGL(wstep_right_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
+                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                           (int)db, (int)wl, (int)wr, (int)d);
       TN_TRY(hip_check(hipGetLastError(), "wstep right"));
       const int32_t a3[2] = {1, 2}, b3[2] = {2, 3};
       TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
