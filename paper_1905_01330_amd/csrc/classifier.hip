@@ -41,7 +41,8 @@ struct ChainArgs {
   int B;
   const float* v_in;      // vector block or NULL (unit vector, exponent 0)
   float* v_out;           // vector block (final vectors), may be NULL
-  float* store;           // n_steps vector blocks of the step inputs, may be NULL
+  float* store;           // step inputs, may be NULL: step st's vectors at store + st * B * CHI,
+  int64_t store_exp;      // its exponents at store + store_exp + st * B
 };
 
 // A "vector block" holds B vectors of length CHI (zero beyond their bond
@@ -54,186 +55,287 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 // FP64 (FP64 matrix cores, v_mfma_f64_16x16x4): a 784-site chain of FP32
 // steps would round the vector at every site, and those errors compound.
 // Site tensors and pixels are read as FP32 and widened exactly.
+// ---------------------------------------------------------------------------
+// Chain kernel.  A workgroup owns 16 samples and has one wave per 16-wide
+// block of output columns (CHI / 16 waves).  Per site it forms its block of
+// the next vector with FP64 16x16x4 MFMAs, writes it to LDS unnormalised
+// together with the block's row maxima, and meets the other waves at one
+// barrier; every wave then derives each row's power-of-two normaliser from
+// the maxima and applies it while reading the vector in the next site.  For
+// CHI <= 128 the site tensor of the next site is loaded into registers
+// while the current site's MFMAs run (two register sets, sites unrolled by
+// two); CHI = 256 loads its tensor in chunks within the site.
 template <int CHI>
-__device__ __forceinline__ void chain_run(const ChainArgs& a, double (*vec)[kRB][CHI + 2], double (*phi)[2], int* expo,
-                                          double* rscale, const float** w_s, int* din_s, int* dout_s, int* site_s) {
+struct ChainSmem {
+  static constexpr int NW = CHI / 16;
+  double vec[2][kRB][CHI + 2];
+  double phi[kMaxSeg][kRB][2];
+  double pmax[2][NW][kRB];
+  const float* w[kMaxSeg];
+  int din[kMaxSeg], dout[kMaxSeg];
+};
+
+template <int CHI, int TYPE>
+struct ChainRegs {
+  // site-tensor registers of one site for the lane's column block
+  static constexpr bool PREFETCH = CHI <= 128;
+  static constexpr int KI0 = CHI / 2;        // type 0: MFMA steps (k = 2a + s in groups of 4)
+  static constexpr int NV1 = CHI / 16;       // type 1: float4 per row slice (z in groups of 4 per lane)
+  float w0[TYPE == 0 && PREFETCH ? KI0 : 1];
+  f32x4c_t wa[TYPE == 1 && PREFETCH ? NV1 : 1], wb[TYPE == 1 && PREFETCH ? NV1 : 1];
+};
+
+template <int CHI, int TYPE>
+__device__ __forceinline__ void chain_load(ChainRegs<CHI, TYPE>& R, const float* W, int col, int g) {
+  if constexpr (ChainRegs<CHI, TYPE>::PREFETCH) {
+    if constexpr (TYPE == 0) {
+#pragma unroll
+      for (int kk = 0; kk < CHI / 2; ++kk) R.w0[kk] = W[(int64_t)(4 * kk + g) * CHI + col];
+    } else {
+      const float* r0 = W + ((int64_t)col * 2) * CHI + g * (CHI / 4);
+#pragma unroll
+      for (int j = 0; j < CHI / 16; ++j) {
+        R.wa[j] = *reinterpret_cast<const f32x4c_t*>(r0 + 4 * j);
+        R.wb[j] = *reinterpret_cast<const f32x4c_t*>(r0 + CHI + 4 * j);
+      }
+    }
+  }
+}
+
+template <int CHI, int TYPE, int SET>
+__device__ __forceinline__ void chain_step(const ChainArgs& a, ChainSmem<CHI>& sm, ChainRegs<CHI, TYPE> (&regs)[2],
+                                           int st, int& cur, double& scl, int& ex, int b0) {
+  constexpr int NW = CHI / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = lane & 15, g = lane >> 4;
+  const int col = wave * 16 + row;          // this lane's output column (type 0: z, type 1: a)
+  const int din = sm.din[st], dout = sm.dout[st];
+  const float* W = sm.w[st];
+  const bool fast = din == CHI && dout == CHI && (TYPE == 0 || (reinterpret_cast<uintptr_t>(W) & 15) == 0);
+  const int nxt = cur ^ 1, par = st & 1;
+  // prefetch the next site's tensor into the other register set
+  if constexpr (ChainRegs<CHI, TYPE>::PREFETCH) {
+    if (st + 1 < a.n_steps) {
+      const float* Wn = sm.w[st + 1];
+      if (sm.din[st + 1] == CHI && sm.dout[st + 1] == CHI &&
+          (TYPE == 0 || (reinterpret_cast<uintptr_t>(Wn) & 15) == 0))
+        chain_load<CHI, TYPE>(regs[SET ^ 1], Wn, col, g);
+    }
+  }
+  f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+  if (TYPE == 0) {
+    // out[r, z] = sum_{a, s} x[r, a] phi[r, s] W[(a s), z]   (k = 2a + s)
+    const double p0 = sm.phi[st][row][0] * scl, p1 = sm.phi[st][row][1] * scl;
+    if (fast && ChainRegs<CHI, TYPE>::PREFETCH) {
+#pragma unroll
+      for (int kk = 0; kk < CHI / 2; ++kk) {
+        const int k = 4 * kk + g;
+        const double xv = sm.vec[cur][row][k >> 1] * ((k & 1) ? p1 : p0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (double)regs[SET].w0[kk], acc0, 0, 0, 0);
+      }
+    } else if (fast) {
+      constexpr int CH = 16;
+      for (int k0 = 0; k0 < CHI / 2; k0 += CH) {
+        float wv[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) wv[q] = W[(int64_t)(4 * (k0 + q) + g) * CHI + col];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int k = 4 * (k0 + q) + g;
+          const double xv = sm.vec[cur][row][k >> 1] * ((k & 1) ? p1 : p0);
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (double)wv[q], acc0, 0, 0, 0);
+        }
+      }
+    } else if (col - row < dout) {
+      const int K4 = (2 * din + 3) >> 2;
+      for (int kk = 0; kk < K4; ++kk) {
+        const int k = 4 * kk + g, aa = k >> 1;
+        double xv = 0.0, wv = 0.0;
+        if (aa < din) {
+          xv = sm.vec[cur][row][aa] * ((k & 1) ? p1 : p0);
+          if (col < dout) wv = (double)W[(int64_t)k * dout + col];
+        }
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wv, acc0, 0, 0, 0);
+      }
+    }
+  } else {
+    // out[r, a] = sum_s phi[r, s] sum_z x[r, z] W[a, s, z]
+    if (fast && ChainRegs<CHI, TYPE>::PREFETCH) {
+      constexpr int KI = CHI / 4;
+#pragma unroll
+      for (int kk = 0; kk < KI; ++kk) {
+        const double xv = sm.vec[cur][row][g * KI + kk] * scl;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (double)regs[SET].wa[kk >> 2][kk & 3], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (double)regs[SET].wb[kk >> 2][kk & 3], acc1, 0, 0, 0);
+      }
+    } else if (fast) {
+      constexpr int KI = CHI / 4;
+      const float* r0 = W + ((int64_t)col * 2) * CHI + g * KI;
+      constexpr int CH = 4;    // float4 per chunk (16 z values of the lane's slice)
+      for (int j0 = 0; j0 < KI / 4; j0 += CH) {
+        f32x4c_t wa[CH], wb[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          wa[j] = *reinterpret_cast<const f32x4c_t*>(r0 + 4 * (j0 + j));
+          wb[j] = *reinterpret_cast<const f32x4c_t*>(r0 + CHI + 4 * (j0 + j));
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4 * CH; ++kk) {
+          const double xv = sm.vec[cur][row][g * KI + 4 * j0 + kk] * scl;
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (double)wa[kk >> 2][kk & 3], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (double)wb[kk >> 2][kk & 3], acc1, 0, 0, 0);
+        }
+      }
+    } else if (col - row < dout) {
+      const int K4 = (din + 3) >> 2;
+      for (int kk = 0; kk < K4; ++kk) {
+        const int z = 4 * kk + g;
+        double xv = 0.0, w0 = 0.0, w1 = 0.0;
+        if (z < din) {
+          xv = sm.vec[cur][row][z] * scl;
+          if (col < dout) {
+            w0 = (double)W[((int64_t)col * 2 + 0) * din + z];
+            w1 = (double)W[((int64_t)col * 2 + 1) * din + z];
+          }
+        }
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, w0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, w1, acc1, 0, 0, 0);
+      }
+    }
+  }
+  // FP64 16x16x4 result: lane (col + 16 g) register r holds row 4 r + g
+  double outv[4];
+  double m[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = r * 4 + g;
+    double v = TYPE == 0 ? acc0[r] : sm.phi[st][rr][0] * acc0[r] + sm.phi[st][rr][1] * acc1[r];
+    if (col >= dout) v = 0.0;
+    outv[r] = v;
+    sm.vec[nxt][rr][col] = v;
+    m[r] = fabs(v);
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m[r] = fmax(m[r], __shfl_xor(m[r], o, 16));
+  if (row == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sm.pmax[par][wave][r * 4 + g] = m[r];
+  }
+  __syncthreads();
+  // the row normaliser 2^-e (e the binary exponent of the row maximum)
+  auto row_exp = [&](int rr) {
+    double mm = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) mm = fmax(mm, sm.pmax[par][w][rr]);
+    return (mm > 0.0 && mm < 1e300) ? ilogb(mm) : 0;
+  };
+  const int e = row_exp(row);
+  // a stored block holds this site's output (the next site's input), normalised
+  float* dst = nullptr;     // vectors of the block to write
+  float* dste = nullptr;    // its exponents
+  if (a.store && st + 1 < a.n_steps) {
+    dst = a.store + (int64_t)(st + 1) * a.B * CHI;
+    dste = a.store + a.store_exp + (int64_t)(st + 1) * a.B;
+  } else if (a.v_out && st + 1 == a.n_steps) {
+    dst = a.v_out;
+    dste = a.v_out + (int64_t)a.B * CHI;
+  }
+  if (dst) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = r * 4 + g, b = b0 + rr;
+      const int er = row_exp(rr);
+      if (b < a.B) dst[(int64_t)b * CHI + col] = (float)ldexp(outv[r], -er);
+    }
+    if (wave == 0 && g == 0 && b0 + row < a.B) dste[b0 + row] = (float)(ex + e);
+  }
+  ex += e;
+  scl = ldexp(1.0, -e);
+  cur = nxt;
+}
+
+template <int CHI, int TYPE>
+__device__ __forceinline__ void chain_run(const ChainArgs& a, ChainSmem<CHI>& sm) {
+  constexpr int NT = CHI / 16 * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = lane & 15, g = lane >> 4;
   const int b0 = blockIdx.x * kRB;
-  const int64_t vb = vblock_floats(a.B, CHI);
   if (b0 >= a.B) return;
-  // per-step tables into LDS with static indices only
   if (tid == 0) {
 #pragma unroll
     for (int j = 0; j < kMaxSeg; ++j)
       if (j < a.n_steps) {
         const int k = a.first_site + a.dir * j;
         const int dl = k == 0 ? 1 : a.chi, dr = k == a.n_sites - 1 ? 1 : a.chi;
-        w_s[j] = a.w[j];
-        din_s[j] = a.step_type == 0 ? dl : dr;
-        dout_s[j] = a.step_type == 0 ? dr : dl;
-        site_s[j] = k;
+        sm.w[j] = a.w[j];
+        sm.din[j] = TYPE == 0 ? dl : dr;
+        sm.dout[j] = TYPE == 0 ? dr : dl;
       }
   }
-  for (int e = tid; e < kRB * CHI; e += 256) {
+  // feature map of every site of the run
+  for (int e = tid; e < a.n_steps * kRB * 2; e += NT) {
+    const int st = e / (2 * kRB), r = (e >> 1) % kRB, sc = e & 1, b = b0 + r;
+    const int k = a.first_site + a.dir * st;
+    const double p = b < a.B ? (double)a.pixels[(int64_t)b * a.n_sites + k] : 0.0;
+    double sv, cv;
+    sincospi(0.5 * p, &sv, &cv);
+    sm.phi[st][r][sc] = sc == 0 ? cv : sv;
+  }
+  for (int e = tid; e < kRB * CHI; e += NT) {
     const int r = e / CHI, i = e % CHI, b = b0 + r;
     double x = 0.0;
     if (b < a.B) x = a.v_in ? (double)a.v_in[(int64_t)b * CHI + i] : (i == 0 ? 1.0 : 0.0);
-    vec[0][r][i] = x;
+    sm.vec[0][r][i] = x;
   }
-  if (tid < kRB) {
-    const int b = b0 + tid;
-    expo[tid] = (a.v_in && b < a.B) ? (int)a.v_in[(int64_t)a.B * CHI + b] : 0;
+  int ex = (a.v_in && b0 + row < a.B) ? (int)a.v_in[(int64_t)a.B * CHI + b0 + row] : 0;
+  double scl = 1.0;
+  // the first site's input, stored as given
+  if (a.store) {
+    const int col = wave * 16 + row;
+    for (int r = g; r < kRB; r += 4) {
+      const int b = b0 + r;
+      if (b < a.B) {
+        const double x = a.v_in ? (double)a.v_in[(int64_t)b * CHI + col] : (col == 0 ? 1.0 : 0.0);
+        a.store[(int64_t)b * CHI + col] = (float)x;
+      }
+    }
+    if (wave == 0 && g == 0 && b0 + row < a.B) a.store[a.store_exp + b0 + row] = (float)ex;
   }
+  ChainRegs<CHI, TYPE> regs[2];
   __syncthreads();
-
+  if constexpr (ChainRegs<CHI, TYPE>::PREFETCH) {
+    if (sm.din[0] == CHI && sm.dout[0] == CHI && (TYPE == 0 || (reinterpret_cast<uintptr_t>(sm.w[0]) & 15) == 0))
+      chain_load<CHI, TYPE>(regs[0], sm.w[0], wave * 16 + row, g);
+  }
   int cur = 0;
-  const int row = lane & 15, g = lane >> 4;   // 16x16x4 operand lanes: (row | column, k-group)
-  for (int st = 0; st < a.n_steps; ++st) {
-    const int din = din_s[st], dout = dout_s[st];
-    const float* W = w_s[st];
-    if (tid < 2 * kRB) {
-      const int r = tid >> 1, sc = tid & 1, b = b0 + r;
-      const double p = b < a.B ? (double)a.pixels[(int64_t)b * a.n_sites + site_s[st]] : 0.0;
-      double sv, cv;
-      sincospi(0.5 * p, &sv, &cv);
-      phi[r][sc] = sc == 0 ? cv : sv;
-    }
-    if (a.store) {
-      float* dst = a.store + st * vb;
-      for (int e = tid; e < kRB * CHI; e += 256) {
-        const int r = e / CHI, i = e % CHI, b = b0 + r;
-        if (b < a.B) dst[(int64_t)b * CHI + i] = (float)vec[cur][r][i];
-      }
-      if (tid < kRB && b0 + tid < a.B) dst[(int64_t)a.B * CHI + b0 + tid] = (float)expo[tid];
-    }
-    __syncthreads();
-    const int nxt = cur ^ 1;
-    if (a.step_type == 0) {
-      // out[r, z] = sum_{a < din, s} vec[r, a] phi[r, s] W[(a s), z]   (k = 2a + s)
-      const int nb = (dout + 15) >> 4;
-      for (int blk = wave; blk < nb; blk += 4) {
-        const int z = blk * 16 + row;
-        f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-        if (din == CHI && dout == CHI) {
-#pragma unroll 8
-          for (int kk = 0; kk < CHI / 2; ++kk) {
-            const int k = 4 * kk + g;
-            const double xv = vec[cur][row][k >> 1] * phi[row][k & 1];
-            const double wv = (double)W[(int64_t)k * CHI + z];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wv, acc, 0, 0, 0);
-          }
-        } else {
-          const int K4 = (2 * din + 3) >> 2;
-          for (int kk = 0; kk < K4; ++kk) {
-            const int k = 4 * kk + g;
-            const int aa = k >> 1;
-            double xv = 0.0, wv = 0.0;
-            if (aa < din) {
-              xv = vec[cur][row][aa] * phi[row][k & 1];
-              if (z < dout) wv = (double)W[(int64_t)k * dout + z];
-            }
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wv, acc, 0, 0, 0);
-          }
-        }
-        if (z < dout) {
-          // FP64 16x16x4 result: lane (col + 16 g) register r holds row 4 r + g
-#pragma unroll
-          for (int r = 0; r < 4; ++r) vec[nxt][r * 4 + g][z] = acc[r];
-        }
-      }
-    } else {
-      // out[r, a] = sum_s phi[r, s] sum_{z < din} vec[r, z] W[a, s, z]
-      const int nb = (dout + 15) >> 4;
-      for (int blk = wave; blk < nb; blk += 4) {
-        const int aa = blk * 16 + row;
-        f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-        if (din == CHI && dout == CHI) {
-#pragma unroll 8
-          for (int kk = 0; kk < CHI / 4; ++kk) {
-            const int z = 4 * kk + g;
-            const double xv = vec[cur][row][z];
-            const double w0 = (double)W[((int64_t)aa * 2 + 0) * CHI + z];
-            const double w1 = (double)W[((int64_t)aa * 2 + 1) * CHI + z];
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, w0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, w1, acc1, 0, 0, 0);
-          }
-        } else {
-          const int K4 = (din + 3) >> 2;
-          for (int kk = 0; kk < K4; ++kk) {
-            const int z = 4 * kk + g;
-            double xv = 0.0, w0 = 0.0, w1 = 0.0;
-            if (z < din) {
-              xv = vec[cur][row][z];
-              if (aa < dout) {
-                w0 = (double)W[((int64_t)aa * 2 + 0) * din + z];
-                w1 = (double)W[((int64_t)aa * 2 + 1) * din + z];
-              }
-            }
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, w0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, w1, acc1, 0, 0, 0);
-          }
-        }
-        if (aa < dout) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int rr = r * 4 + g;
-            vec[nxt][rr][aa] = phi[rr][0] * acc0[r] + phi[rr][1] * acc1[r];
-          }
-        }
-      }
-    }
-    for (int e = tid; e < kRB * CHI; e += 256) {
-      const int r = e / CHI, i = e % CHI;
-      if (i >= dout) vec[nxt][r][i] = 0.0;
-    }
-    __syncthreads();
-    // exact per-sample rescale by 2^-e, e the binary exponent of max|v|
-    {
-      const int r = tid >> 4, t = tid & 15;
-      double m = 0.0;
-      for (int i = t; i < dout; i += 16) m = fmax(m, fabs(vec[nxt][r][i]));
-#pragma unroll
-      for (int o = 8; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 16));
-      if (t == 0) {
-        int e = 0;
-        if (m > 0.0 && m < 1e300) e = ilogb(m);
-        expo[r] += e;
-        rscale[r] = ldexp(1.0, -e);
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < kRB * dout; e += 256) {
-      const int r = e / dout, i = e % dout;
-      vec[nxt][r][i] *= rscale[r];
-    }
-    __syncthreads();
-    cur = nxt;
+  for (int st = 0; st < a.n_steps; st += 2) {
+    chain_step<CHI, TYPE, 0>(a, sm, regs, st, cur, scl, ex, b0);
+    if (st + 1 < a.n_steps) chain_step<CHI, TYPE, 1>(a, sm, regs, st + 1, cur, scl, ex, b0);
   }
-  if (a.v_out) {
-    for (int e = tid; e < kRB * CHI; e += 256) {
-      const int r = e / CHI, i = e % CHI, b = b0 + r;
-      if (b < a.B) a.v_out[(int64_t)b * CHI + i] = (float)vec[cur][r][i];
-    }
-    if (tid < kRB && b0 + tid < a.B) a.v_out[(int64_t)a.B * CHI + b0 + tid] = (float)expo[tid];
-  }
+  // a run of zero sites (never launched) would leave v_out unwritten
 }
 
 // blockIdx.y selects one of up to four independent runs (left and right
 // chains, recomputation and adjoint) advancing in one launch
 template <int CHI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(CHI / 16 * 64)
     chain_kernel(const ChainArgs a0, const ChainArgs a1, const ChainArgs a2, const ChainArgs a3) {
-  __shared__ double vec[2][kRB][CHI + 2];
-  __shared__ double phi[kRB][2];
-  __shared__ int expo[kRB];
-  __shared__ double rscale[kRB];
-  __shared__ const float* w_s[kMaxSeg];
-  __shared__ int din_s[kMaxSeg], dout_s[kMaxSeg], site_s[kMaxSeg];
+  __shared__ ChainSmem<CHI> sm;
   switch (blockIdx.y) {
-    case 0: chain_run<CHI>(a0, vec, phi, expo, rscale, w_s, din_s, dout_s, site_s); break;
-    case 1: chain_run<CHI>(a1, vec, phi, expo, rscale, w_s, din_s, dout_s, site_s); break;
-    case 2: chain_run<CHI>(a2, vec, phi, expo, rscale, w_s, din_s, dout_s, site_s); break;
-    default: chain_run<CHI>(a3, vec, phi, expo, rscale, w_s, din_s, dout_s, site_s); break;
+    case 0:
+      if (a0.step_type == 0) chain_run<CHI, 0>(a0, sm); else chain_run<CHI, 1>(a0, sm);
+      break;
+    case 1:
+      if (a1.step_type == 0) chain_run<CHI, 0>(a1, sm); else chain_run<CHI, 1>(a1, sm);
+      break;
+    case 2:
+      if (a2.step_type == 0) chain_run<CHI, 0>(a2, sm); else chain_run<CHI, 1>(a2, sm);
+      break;
+    default:
+      if (a3.step_type == 0) chain_run<CHI, 0>(a3, sm); else chain_run<CHI, 1>(a3, sm);
+      break;
   }
 }
 
@@ -256,15 +358,18 @@ __global__ void expand_kernel(const float* vblk, const float* wblk_exp, const fl
   }
 }
 
-// One segment of gradient operands at once.  Batch entry j is site
-// k_j = k0 - j:  X_j[b, a, s] = V_j[b, a] Phi_s(x_{b, k_j}) 2^(e_V(b) + e_G(b))
-// with V_j the vector block at vsrc + (n-1-j) vb and e_G the exponents of
-// the block at gsrc + j vb (the GEMM's other operand).  a runs over chi.
-__global__ void expand_seg_kernel(const float* vsrc, const float* gsrc, int64_t vb, int n, int k0,
+// One segment of gradient operands at once.  A segment buffer holds E
+// vector slots of B x pc floats followed by E x B exponents (at + eoff).
+// Batch entry j is site k_j = k0 - j:
+//   X_j[b, a, s] = V_j[b, a] Phi_s(x_{b, k_j}) 2^(e_V(b) + e_G(b))
+// with V_j in slot n-1-j of vsrc and e_G the exponents of slot j of gsrc
+// (the GEMM's other operand).  a runs over chi.
+__global__ void expand_seg_kernel(const float* vsrc, const float* gsrc, int64_t eoff, int n, int k0,
                                   const float* pixels, int n_pix, int B, int pc, int chi, float* x) {
   const int j = blockIdx.y;
-  const float* v = vsrc + (int64_t)(n - 1 - j) * vb;
-  const float* ge = gsrc + (int64_t)j * vb + (int64_t)B * pc;
+  const float* v = vsrc + (int64_t)(n - 1 - j) * B * pc;
+  const float* ve = vsrc + eoff + (int64_t)(n - 1 - j) * B;
+  const float* ge = gsrc + eoff + (int64_t)j * B;
   const int k = k0 - j;
   float* xj = x + (int64_t)j * B * chi * 2;
   const int64_t total = (int64_t)B * chi * 2;
@@ -274,7 +379,7 @@ __global__ void expand_seg_kernel(const float* vsrc, const float* gsrc, int64_t 
     const int b = (int)(ba / chi), aa = (int)(ba % chi);
     float sv, cv;
     sincospif(0.5f * pixels[(int64_t)b * n_pix + k], &sv, &cv);
-    const int ex = (int)v[(int64_t)B * pc + b] + (int)ge[b];
+    const int ex = (int)ve[b] + (int)ge[b];
     xj[e] = ldexpf(v[(int64_t)b * pc + aa] * (s == 0 ? cv : sv), ex);
   }
 }
@@ -284,12 +389,14 @@ struct ScatterArgs {
   int64_t st[kMaxSeg][3];
 };
 
-// dA_{k_j}[a, s, z] = G_j[a, s, z] for a < d_left(k_j), z < d_right(k_j)
-__global__ void scatter_grad_kernel(const float* gbuf, int n, int k0, int n_sites, int chi, const ScatterArgs sa) {
+// dA_{k_j}[a, s, z] = sum_c G_{j,c}[a, s, z] (the S batch chunks, summed in
+// a fixed order) for a < d_left(k_j), z < d_right(k_j)
+__global__ void scatter_grad_kernel(const float* gbuf, int n, int S, int k0, int n_sites, int chi, const ScatterArgs sa) {
   const int j = blockIdx.y;
   const int k = k0 - j;
   const int dl = k == 0 ? 1 : chi, dr = k == n_sites - 1 ? 1 : chi;
-  const float* src = gbuf + (int64_t)j * chi * 2 * chi;
+  const int64_t blk = (int64_t)chi * 2 * chi;
+  const float* src = gbuf + (int64_t)j * S * blk;
   float* dst = nullptr;
   int64_t s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
@@ -305,7 +412,10 @@ __global__ void scatter_grad_kernel(const float* gbuf, int n, int k0, int n_site
     const int z = (int)(e % dr);
     const int64_t as = e / dr;
     const int sidx = (int)(as & 1), aa = (int)(as >> 1);
-    dst[aa * s0 + sidx * s1 + z * s2] = src[((int64_t)aa * 2 + sidx) * chi + z];
+    const int64_t o = ((int64_t)aa * 2 + sidx) * chi + z;
+    float v = 0.f;
+    for (int c = 0; c < S; ++c) v += src[c * blk + o];
+    dst[aa * s0 + sidx * s1 + z * s2] = v;
   }
 }
 
@@ -417,7 +527,18 @@ struct Geometry {
   std::vector<int> right_b;    // right boundaries N = t_0 > ... > t_m = c + 1
   int64_t vb;                  // floats per vector block
   size_t ckpt_floats;
+  int S;                       // batch chunks of the weight-gradient GEMMs
 };
+
+// Batch chunks for the weight-gradient GEMMs (K = batch is long, the output
+// 2 chi x chi small): split the batch while it divides evenly, the chunks
+// keep at least 64 samples and a segment has fewer than 2048 64 x 64 tiles.
+int grad_chunks(int B, int chi, int E) {
+  const int64_t tiles = (int64_t)((2 * chi + 63) / 64) * ((chi + 63) / 64);
+  int S = 1;
+  while (S < 16 && B % (2 * S) == 0 && B / (2 * S) >= 64 && (int64_t)E * S * tiles < 2048) S *= 2;
+  return S;
+}
 
 int pad_of(int chi) {
   for (int p : {16, 32, 64, 128, 256})
@@ -444,6 +565,7 @@ int32_t geometry(int32_t N, int32_t c, int32_t L, int32_t B, int32_t chi, int32_
   for (int t = N; t > c + 1; t -= E) g.right_b.push_back(t);
   g.right_b.push_back(c + 1);
   g.vb = vblock_floats(B, g.pad_chi);
+  g.S = grad_chunks(B, chi, E);
   g.ckpt_floats = (size_t)(g.left_b.size() + g.right_b.size()) * g.vb;
   return TN_OK;
 }
@@ -471,7 +593,7 @@ WsLayout ws_layout(const Geometry& g) {
     w.seg_v[side] = o; o += al(E * vb);
     w.seg_g[side] = o; o += al(E * vb);
     w.xseg[side] = o; o += al(E * (size_t)g.B * g.chi * 2 * 4);
-    w.gbuf[side] = o; o += al(E * (size_t)g.chi * 2 * g.chi * 4);
+    w.gbuf[side] = o; o += al(E * (size_t)g.S * g.chi * 2 * g.chi * 4);
   }
   w.part = o; o += al((size_t)g.B * 8);
   w.total = o;
@@ -516,6 +638,7 @@ ChainArgs chain_args(const Geometry& g, const tn_tensor* sites, const float* pix
   a.v_in = v_in;
   a.v_out = v_out;
   a.store = store;
+  a.store_exp = (int64_t)g.E * g.B * g.pad_chi;   // segment buffers: E vector slots, then E x B exponents
   for (int j = 0; j < n_steps; ++j) a.w[j] = static_cast<const float*>(sites[first_site + dir * j].data);
   return a;
 }
@@ -529,12 +652,13 @@ int32_t launch_chains(const Geometry& g, const std::vector<ChainArgs>& runs, hip
   if (r.size() > 4) return fail(TN_ERR_INVALID_ARGUMENT, "at most four chain runs per launch");
   const dim3 grid((unsigned)((g.B + kRB - 1) / kRB), (unsigned)r.size());
   while (r.size() < 4) r.push_back(r[0]);
+  // one wave per 16 output columns
   switch (g.pad_chi) {
-    case 16: hipLaunchKernelGGL(chain_kernel<16>, grid, dim3(256), 0, st, r[0], r[1], r[2], r[3]); break;
-    case 32: hipLaunchKernelGGL(chain_kernel<32>, grid, dim3(256), 0, st, r[0], r[1], r[2], r[3]); break;
+    case 16: hipLaunchKernelGGL(chain_kernel<16>, grid, dim3(64), 0, st, r[0], r[1], r[2], r[3]); break;
+    case 32: hipLaunchKernelGGL(chain_kernel<32>, grid, dim3(128), 0, st, r[0], r[1], r[2], r[3]); break;
     case 64: hipLaunchKernelGGL(chain_kernel<64>, grid, dim3(256), 0, st, r[0], r[1], r[2], r[3]); break;
-    case 128: hipLaunchKernelGGL(chain_kernel<128>, grid, dim3(256), 0, st, r[0], r[1], r[2], r[3]); break;
-    default: hipLaunchKernelGGL(chain_kernel<256>, grid, dim3(256), 0, st, r[0], r[1], r[2], r[3]); break;
+    case 128: hipLaunchKernelGGL(chain_kernel<128>, grid, dim3(512), 0, st, r[0], r[1], r[2], r[3]); break;
+    default: hipLaunchKernelGGL(chain_kernel<256>, grid, dim3(1024), 0, st, r[0], r[1], r[2], r[3]); break;
   }
   return hip_check(hipGetLastError(), "chain kernel");
 }
@@ -547,22 +671,24 @@ int32_t launch_chain(const Geometry& g, const tn_tensor* sites, const float* pix
 
 // Weight gradients of one segment: dA_{k_j} = sum_b X_j[b, (a s)] G_j[b, z]
 // for j < n, k_j = k0 - j, X_j formed from vsrc (see expand_seg_kernel) and
-// G_j the vector block at gsrc + j vb; one batched GEMM into gbuf, then a
-// scatter into the caller's gradient tensors.
+// G_j the vectors of slot j of gsrc.  One batched GEMM over (j, chunk c of
+// the batch) into S partial blocks per site, then a scatter that sums them
+// into the caller's gradient tensors.
 int32_t segment_grads(const Geometry& g, const float* vsrc, const float* gsrc, int n, int k0, const float* px,
                       float* xseg, float* gbuf, tn_tensor* dsites, int32_t prec, hipStream_t st) {
   if (n <= 0) return TN_OK;
-  const int B = g.B, chi = g.chi, pc = g.pad_chi;
+  const int B = g.B, chi = g.chi, pc = g.pad_chi, S = g.S, Bc = B / S;
+  const int64_t eoff = (int64_t)g.E * B * pc;
   hipLaunchKernelGGL(expand_seg_kernel, dim3(std::min<unsigned>(blocks_of((int64_t)B * chi * 2), 2048), n), dim3(256),
-                     0, st, vsrc, gsrc, g.vb, n, k0, px, g.N, B, pc, chi, xseg);
+                     0, st, vsrc, gsrc, eoff, n, k0, px, g.N, B, pc, chi, xseg);
   TN_TRY(hip_check(hipGetLastError(), "expand segment"));
-  tn_tensor xv = make_view(xseg, TN_F32, {B, chi, 2});
+  tn_tensor xv = make_view(xseg, TN_F32, {Bc, chi, 2});
   tn_tensor gv;
   std::memset(&gv, 0, sizeof(gv));
   gv.data = const_cast<float*>(gsrc);
   gv.dtype = TN_F32;
   gv.rank = 2;
-  gv.shape[0] = B;
+  gv.shape[0] = Bc;
   gv.shape[1] = chi;
   gv.stride[0] = pc;
   gv.stride[1] = 1;
@@ -570,9 +696,10 @@ int32_t segment_grads(const Geometry& g, const float* vsrc, const float* gsrc, i
   const int32_t pa[1] = {0}, pb[1] = {0};
   GemmDesc d;
   TN_TRY(plan_gemm(xv, gv, 1, pa, pb, ov, d));
-  d.batch = n;
-  d.a_bs = (int64_t)B * chi * 2;
-  d.b_bs = g.vb;
+  // batch entry j * S + c: X_j rows and G_j rows of chunk c, partial block (j, c)
+  d.batch = n * S;
+  d.a_bs = (int64_t)Bc * chi * 2;
+  d.b_bs = (int64_t)Bc * pc;
   d.c_bs = (int64_t)chi * 2 * chi;
   choose_modes(d);
   TN_TRY(launch_gemm(d, prec, st));
@@ -583,7 +710,7 @@ int32_t segment_grads(const Geometry& g, const float* vsrc, const float* gsrc, i
     sa.dst[j] = static_cast<float*>(t.data);
     for (int q = 0; q < 3; ++q) sa.st[j][q] = t.stride[q];
   }
-  hipLaunchKernelGGL(scatter_grad_kernel, dim3(blocks_of((int64_t)chi * 2 * chi), n), dim3(256), 0, st, gbuf, n, k0,
+  hipLaunchKernelGGL(scatter_grad_kernel, dim3(blocks_of((int64_t)chi * 2 * chi), n), dim3(256), 0, st, gbuf, n, S, k0,
                      g.N, chi, sa);
   return hip_check(hipGetLastError(), "scatter gradients");
 }
