@@ -153,6 +153,19 @@ int32_t tn_mps_inner_batched_workspace(int32_t n_chains, const int32_t* site_off
 int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets,
                              const tn_tensor* psi_sites, const tn_tensor* phi_sites, double* out2,
                              void* workspace, size_t ws_bytes, int32_t prec, void* stream);
+/* The same call in two parts, so that the launches can be recorded in a
+ * HIP graph and replayed.  _upload writes the work tables (chain records,
+ * grouped-GEMM problems) into the workspace and waits for the copy to
+ * finish on `stream` (not capturable).  _launch only launches kernels on
+ * `stream` (capturable); it uses the tables of the last _upload into the
+ * same workspace, which must have been made with the same chains, tensors
+ * and workspace.  Errors as tn_mps_inner_batched. */
+int32_t tn_mps_inner_batched_upload(int32_t n_chains, const int32_t* site_offsets,
+                                    const tn_tensor* psi_sites, const tn_tensor* phi_sites,
+                                    void* workspace, size_t ws_bytes, void* stream);
+int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offsets,
+                                    const tn_tensor* psi_sites, const tn_tensor* phi_sites, double* out2,
+                                    void* workspace, size_t ws_bytes, int32_t prec, void* stream);
 
 /* ---------------------------------------------------------------------
  * Operator environments of <psi|H|psi> for an MPO H.  psi[k]: TN_F32

@@ -9,6 +9,7 @@ from .api import (  # noqa: F401
     ClassifierFunction,
     MPSClassifier,
     EnvSweep,
+    Graph,
     contract_between,
     contract_network,
     mps_env_sweep,

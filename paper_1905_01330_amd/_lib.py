@@ -58,6 +58,8 @@ _PROTOS = {
     "tn_mps_inner": (I32, [I32, TP, TP, P, P, SZ, I32, P]),
     "tn_mps_inner_batched_workspace": (I32, [I32, I32P, TP, TP, C.POINTER(SZ)]),
     "tn_mps_inner_batched": (I32, [I32, I32P, TP, TP, P, P, SZ, I32, P]),
+    "tn_mps_inner_batched_upload": (I32, [I32, I32P, TP, TP, P, SZ, P]),
+    "tn_mps_inner_batched_launch": (I32, [I32, I32P, TP, TP, P, P, SZ, I32, P]),
     "tn_mps_env_sweep_workspace": (I32, [I32, TP, TP, C.POINTER(SZ)]),
     "tn_mps_env_sweep": (I32, [I32, TP, TP, TP, TP, P, I32, P, SZ, I32, P]),
     "tn_mps_left_canonicalize_workspace": (I32, [I32, TP, C.POINTER(SZ)]),

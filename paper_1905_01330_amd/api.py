@@ -112,7 +112,9 @@ def mps_inner(psi, phi, prec="fp32"):
 
 
 class BatchedInner:
-    """Prepared uneven batch: descriptors are built once, run() can be repeated."""
+    """Prepared uneven batch: descriptors are built and the work tables
+    uploaded once; run() only launches kernels, so it can be repeated and
+    recorded in a Graph."""
 
     def __init__(self, chains, prec="fp32"):
         self.psi = [t for p, _ in chains for t in p]
@@ -130,11 +132,41 @@ class BatchedInner:
         self.ws = _workspace(self.nbytes, dev)
         self.out2 = torch.empty((self.n, 2), dtype=torch.float64, device=dev)
         self.prec = L.prec_code(prec)
+        L.check(L.lib().tn_mps_inner_batched_upload(self.n, self.offs, self.dp, self.dq, C.c_void_p(self.ws.data_ptr()),
+                                                    self.nbytes, L.stream_ptr()))
 
     def run(self):
-        L.check(L.lib().tn_mps_inner_batched(self.n, self.offs, self.dp, self.dq, C.c_void_p(self.out2.data_ptr()),
-                                             C.c_void_p(self.ws.data_ptr()), self.nbytes, self.prec, L.stream_ptr()))
+        L.check(L.lib().tn_mps_inner_batched_launch(self.n, self.offs, self.dp, self.dq,
+                                                    C.c_void_p(self.out2.data_ptr()), C.c_void_p(self.ws.data_ptr()),
+                                                    self.nbytes, self.prec, L.stream_ptr()))
         return self.out2
+
+
+class Graph:
+    """A sequence of library calls recorded once as a HIP graph and replayed.
+
+    fn runs once eagerly on a side stream (so workspaces and tile choices
+    exist), then once under stream capture.  Calls that only launch kernels
+    can be recorded: contract_between, trace_edge, outer_product,
+    contract_network, mps_inner, BatchedInner.run, EnvSweep.run and the
+    classifier's forward and backward (the tile tuner never times
+    candidates while a stream is capturing).  Tensors that fn allocates come
+    from the graph's memory pool and are rewritten by every replay.
+    """
+
+    def __init__(self, fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.result = fn()
+
+    def replay(self):
+        self.graph.replay()
+        return self.result
 
 
 def mps_inner_batched(chains, prec="fp32"):

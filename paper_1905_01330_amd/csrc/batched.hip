@@ -235,11 +235,8 @@ int32_t tn_mps_inner_batched_workspace(int32_t n_chains, const int32_t* site_off
   return TN_OK;
 }
 
-int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
-                             const tn_tensor* phi_sites, double* out2, void* workspace, size_t ws_bytes, int32_t prec,
-                             void* stream) {
-  if (!out2) return fail(TN_ERR_INVALID_ARGUMENT, "out2 is NULL");
-  if (prec < 0 || prec > 3) return fail(TN_ERR_UNSUPPORTED, "unknown precision %d", prec);
+int32_t tn_mps_inner_batched_upload(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
+                                    const tn_tensor* phi_sites, void* workspace, size_t ws_bytes, void* stream) {
   BatchPlan P;
   TN_TRY(build(n_chains, site_offsets, psi_sites, phi_sites, nullptr, P));
   if (ws_bytes < P.total || !workspace) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", P.total);
@@ -247,23 +244,50 @@ int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets, cons
   char* ws = static_cast<char*>(workspace);
   TN_TRY(build(n_chains, site_offsets, psi_sites, phi_sites, ws, Q));
   hipStream_t st = static_cast<hipStream_t>(stream);
+  TN_TRY(hip_check(hipMemcpyAsync(ws + Q.chain_tab, Q.chains.data(), Q.chains.size() * sizeof(ChainRec),
+                                  hipMemcpyHostToDevice, st),
+                   "chain table upload"));
+  TN_TRY(hip_check(hipMemcpyAsync(ws + Q.prob_tab, Q.probs.data(), Q.probs.size() * sizeof(Gemm2D), hipMemcpyHostToDevice, st),
+                   "problem table upload"));
+  TN_TRY(hip_check(hipMemcpyAsync(ws + Q.tile_tab, Q.tstart.data(), Q.tstart.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, st),
+                   "tile table upload"));
+  // the host tables are released when this call returns
+  return hip_check(hipStreamSynchronize(st), "table upload");
+}
+
+int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
+                                    const tn_tensor* phi_sites, double* out2, void* workspace, size_t ws_bytes,
+                                    int32_t prec, void* stream) {
+  if (!out2) return fail(TN_ERR_INVALID_ARGUMENT, "out2 is NULL");
+  if (prec < 0 || prec > 3) return fail(TN_ERR_UNSUPPORTED, "unknown precision %d", prec);
+  BatchPlan P;
+  TN_TRY(build(n_chains, site_offsets, psi_sites, phi_sites, nullptr, P));
+  if (ws_bytes < P.total || !workspace) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", P.total);
+  // the host-side launch list is rebuilt (no device work); the tables are the upload's
+  BatchPlan Q;
+  char* ws = static_cast<char*>(workspace);
+  TN_TRY(build(n_chains, site_offsets, psi_sites, phi_sites, ws, Q));
+  hipStream_t st = static_cast<hipStream_t>(stream);
   ChainRec* d_chains = reinterpret_cast<ChainRec*>(ws + Q.chain_tab);
   Gemm2D* d_probs = reinterpret_cast<Gemm2D*>(ws + Q.prob_tab);
   int32_t* d_tiles = reinterpret_cast<int32_t*>(ws + Q.tile_tab);
-  TN_TRY(hip_check(hipMemcpyAsync(d_chains, Q.chains.data(), Q.chains.size() * sizeof(ChainRec), hipMemcpyHostToDevice, st),
-                   "chain table upload"));
-  TN_TRY(hip_check(hipMemcpyAsync(d_probs, Q.probs.data(), Q.probs.size() * sizeof(Gemm2D), hipMemcpyHostToDevice, st),
-                   "problem table upload"));
-  TN_TRY(hip_check(hipMemcpyAsync(d_tiles, Q.tstart.data(), Q.tstart.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
-                   "tile table upload"));
-  // the host tables are released when this call returns
-  TN_TRY(hip_check(hipStreamSynchronize(st), "table upload"));
   hipLaunchKernelGGL(batched_init_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains);
   TN_TRY(hip_check(hipGetLastError(), "batched init"));
   for (const Launch& L : Q.launches)
     TN_TRY(launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off, L.n_probs, L.tiles, prec, L.cfg, st));
   hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains, out2);
   return hip_check(hipGetLastError(), "batched finish");
+}
+
+int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets, const tn_tensor* psi_sites,
+                             const tn_tensor* phi_sites, double* out2, void* workspace, size_t ws_bytes, int32_t prec,
+                             void* stream) {
+  if (!out2) return fail(TN_ERR_INVALID_ARGUMENT, "out2 is NULL");
+  if (prec < 0 || prec > 3) return fail(TN_ERR_UNSUPPORTED, "unknown precision %d", prec);
+  TN_TRY(tn_mps_inner_batched_upload(n_chains, site_offsets, psi_sites, phi_sites, workspace, ws_bytes, stream));
+  return tn_mps_inner_batched_launch(n_chains, site_offsets, psi_sites, phi_sites, out2, workspace, ws_bytes, prec,
+                                     stream);
 }
 
 }  // extern "C"

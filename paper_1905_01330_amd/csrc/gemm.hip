@@ -24,7 +24,7 @@ static const Cfg kCfgs[] = {
     {256, 128, 16, 2, 2, 0.75f}, {128, 256, 16, 2, 2, 0.80f}, {128, 128, 16, 2, 2, 1.00f},
     {128, 128, 32, 2, 2, 0.95f}, {128, 64, 32, 2, 2, 0.70f},  {64, 128, 32, 2, 2, 0.70f},
     {64, 64, 32, 2, 2, 0.55f},   {32, 32, 32, 1, 1, 0.25f},  {160, 128, 16, 1, 4, 1.00f},
-    {128, 160, 16, 4, 1, 1.00f},
+    {128, 160, 16, 4, 1, 1.00f},   {160, 256, 32, 1, 8, 2.00f}, {256, 160, 32, 8, 1, 2.00f},
 };
 static constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -47,12 +47,17 @@ static GroupedFn pick_grouped(int prec, int cfg) { return grouped_fn_prec(prec, 
 
 static int g_forced_cfg = -1;
 
+// eight-wave tiles have a fixed 256-register budget that the run-time-mode
+// gathers exceed: they serve the fast gathers only
+static bool cfg_allowed(const GemmDesc& d, int c) { return kCfgs[c].wm * kCfgs[c].wn < 8 || gemm_variant(d) != 0; }
+
 static int heuristic_cfg(const GemmDesc& d) {
   if (g_forced_cfg >= 0) return g_forced_cfg;
   constexpr int kSlots = 256;  // one workgroup per compute unit for the large tiles
   double best = 1e300;
-  int best_c = kNumCfgs - 1;
+  int best_c = 7;   // 32 x 32 tiles fit every problem
   for (int c = 0; c < kNumCfgs; ++c) {
+    if (!cfg_allowed(d, c)) continue;
     const Cfg& g = kCfgs[c];
     const int64_t tiles = (int64_t)((d.M + g.bm - 1) / g.bm) * ((d.N + g.bn - 1) / g.bn) * d.batch;
     const int64_t rounds = (tiles + kSlots - 1) / kSlots;
@@ -96,7 +101,8 @@ static int tune_cfg(GemmDesc& d, int32_t prec, hipStream_t st) {
   float best_ms = 1e30f;
   for (int c = 0; c < kNumCfgs; ++c) {
     const Cfg& g = kCfgs[c];
-    if ((int64_t)g.bm * g.bn > 4ll * d.M * d.N && c != kNumCfgs - 1) continue;  // mostly padding
+    if ((int64_t)g.bm * g.bn > 4ll * d.M * d.N && c != 7) continue;  // mostly padding (32 x 32 always runs)
+    if (!cfg_allowed(d, c)) continue;
     if (launch_gemm_cfg(d, prec, c, st) != TN_OK) continue;  // warm-up
     hipEventRecord(e0, st);
     for (int r = 0; r < 3; ++r) launch_gemm_cfg(d, prec, c, st);

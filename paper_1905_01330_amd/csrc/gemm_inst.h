@@ -109,6 +109,8 @@ GemmFn gemm_fn_modes(int cfg) {
     case 6: return gemm_kernel<P, 64, 64, 32, 2, 2, AM, BM_>;
     case 8: return gemm_kernel<P, 160, 128, 16, 1, 4, AM, BM_>;
     case 9: return gemm_kernel<P, 128, 160, 16, 4, 1, AM, BM_>;
+    case 10: return gemm_kernel<P, 160, 256, 32, 1, 8, AM, BM_>;
+    case 11: return gemm_kernel<P, 256, 160, 32, 8, 1, AM, BM_>;
     default: return gemm_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }

@@ -318,7 +318,7 @@ struct OperandLoader {
 //   MODE = LOAD_KVEC : k is the unit-stride axis, 1 x 4 micro-blocks
 //   MODE = LOAD_MNVEC: the row axis is unit-stride, 4 x 4 micro-blocks,
 //                      transposed in registers before the LDS store
-template <int P, int R, int BK, int NT, int MODE>
+template <int P, int R, int BK, int NT, int MODE, int DEPTH = 2>
 struct FastLoader {
   // m/n-contiguous operands are read as 4 rows x KD k micro-blocks (KD float4
   // loads, transposed in registers).  KD = 4 when the 4 x 4 blocks cover the
@@ -330,7 +330,7 @@ struct FastLoader {
   static constexpr bool EXACT = NMB % NT == 0;
   static constexpr int NREG = MODE == LOAD_KVEC ? NV : KD * NV;
 
-  f32x4_t st[2][NREG];   // two stages in flight (set = stage parity)
+  f32x4_t st[DEPTH][NREG];   // DEPTH stages in flight (set = stage parity)
   const float* ptr[NV];
   int kq[NV];
   int64_t sk;
@@ -483,6 +483,9 @@ struct GemmTile {
   // each block's term products of a stage form one zero-based chain that is
   // added to the accumulator at once (more VALU adds, half the registers).
   static constexpr bool CHAIN = PrecInfo<P>::planes > 1 && TM * TN > 4 && TM * TN * 16 + 32 <= 128;
+  // global loads run DEPTH stages ahead; workgroups of eight waves (two per
+  // SIMD by construction, a fixed 256-register budget) keep one stage ahead
+  static constexpr int DEPTH = NT >= 512 ? 1 : 2;
   static constexpr int TMT = PrecInfo<P>::planes > 1 && !CHAIN ? TM : 1;
   static constexpr int TNT = PrecInfo<P>::planes > 1 && !CHAIN ? TN : 1;
 
@@ -501,10 +504,22 @@ struct GemmTile {
   struct Nothing {
     __device__ __forceinline__ void operator()() const {}
   };
-  template <typename F = Nothing>
+  // LATE: `between` runs after the MFMAs (its data is still in flight when
+  // the stage starts, as with one stage of prefetch)
+  template <bool LATE = false, typename F = Nothing>
   __device__ static __forceinline__ void compute(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN],
                                                  f32x16_t (&tmp)[TMT][TNT], bool first, bool flush, int wm_off,
                                                  int wn_off, const F& between = F()) {
+    compute_body(sa, sb, acc, tmp, first, flush, wm_off, wn_off, [&]() {
+      if constexpr (!LATE) between();
+    });
+    if constexpr (LATE) between();
+  }
+
+  template <typename F>
+  __device__ static __forceinline__ void compute_body(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN],
+                                                      f32x16_t (&tmp)[TMT][TNT], bool first, bool flush, int wm_off,
+                                                      int wn_off, const F& between) {
     const int lane = threadIdx.x & 63;
     const int lr = lane & 31, lh = lane >> 5;
     if constexpr (!PrecInfo<P>::bf) {
@@ -714,28 +729,31 @@ struct GemmTile {
       }
       if (nk % FLUSH != 0) flush_tmp(acc, tmp);
     } else {
-      FastLoader<P, BM, BK, NT, AMODE> la;
-      FastLoader<P, BN, BK, NT, BMODE> lb;
+      FastLoader<P, BM, BK, NT, AMODE, DEPTH> la;
+      FastLoader<P, BN, BK, NT, BMODE, DEPTH> lb;
       la.init(d.a + bz * d.a_bs, d.gm, m0, d.M, d.gk.s[0][0], d.K);
       lb.init(d.b + bz * d.b_bs, d.gn, n0, d.N, d.gk.s[1][0], d.K);
       const int nfull = d.K / BK;
-      // Software pipeline: global loads run two stages ahead in two register
-      // sets (set = stage parity); while stage kt's MFMAs run, stage kt+1 is
-      // split and stored into the other LDS buffer.  One barrier per stage.
+      // Software pipeline: global loads run DEPTH stages ahead in DEPTH
+      // register sets (set = stage parity when DEPTH = 2); while stage kt's
+      // MFMAs run, stage kt+1 is split and stored into the other LDS buffer.
+      // One barrier per stage.
       la.template load_stage<0>(0, nfull, nk);
       lb.template load_stage<0>(0, nfull, nk);
-      la.template load_stage<1>(1, nfull, nk);
-      lb.template load_stage<1>(1, nfull, nk);
+      if constexpr (DEPTH == 2) {
+        la.template load_stage<1>(1, nfull, nk);
+        lb.template load_stage<1>(1, nfull, nk);
+      }
       la.template store<0>(smem);
       lb.template store<0>(smem + bytesA);
       __syncthreads();
       static_assert(FLUSH % 2 == 0 || FLUSH == 1, "stage groups must keep the register-set parity static");
       constexpr int G = FLUSH == 1 ? 2 : FLUSH;   // stages per unrolled group (even)
       int kt0 = 0;
-      // steady state: every stage of the group loads a full stage two ahead
+      // steady state: every stage of the group loads a full stage DEPTH ahead
       // and stores the next one, so a stage is one straight-line block that
       // the scheduler can interleave (loads, split, LDS traffic and MFMAs)
-      for (; kt0 + G + 1 < nfull; kt0 += G) {
+      for (; kt0 + G - 1 + DEPTH < nfull; kt0 += G) {
 #pragma unroll
         for (int s = 0; s < G; ++s) {
           const int kt = kt0 + s;
@@ -743,7 +761,15 @@ struct GemmTile {
           char* nxt = smem + ((s + 1) & 1) * stage;
           const bool first = FLUSH == 1 ? true : s == 0;
           const bool flush = FLUSH == 1 ? true : s == FLUSH - 1;
-          if (s & 1) {
+          if constexpr (DEPTH == 1) {
+            la.template load<false, 0>((kt + 1) * BK);
+            lb.template load<false, 0>((kt + 1) * BK);
+            auto st_next = [&]() {
+              la.template store<0>(nxt);
+              lb.template store<0>(nxt + bytesA);
+            };
+            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+          } else if (s & 1) {
             la.template load<false, 1>((kt + 2) * BK);
             lb.template load<false, 1>((kt + 2) * BK);
             auto st_next = [&]() {
@@ -773,7 +799,17 @@ struct GemmTile {
             char* nxt = smem + ((s + 1) & 1) * stage;
             const bool first = FLUSH == 1 ? true : s == 0;
             const bool flush = FLUSH == 1 ? true : s == FLUSH - 1;
-            if (s & 1) {
+            if constexpr (DEPTH == 1) {
+              la.template load_stage<0>(kt + 1, nfull, nk);
+              lb.template load_stage<0>(kt + 1, nfull, nk);
+              auto st_next = [&]() {
+                if (kt + 1 < nk) {
+                  la.template store<0>(nxt);
+                  lb.template store<0>(nxt + bytesA);
+                }
+              };
+              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+            } else if (s & 1) {
               la.template load_stage<1>(kt + 2, nfull, nk);
               lb.template load_stage<1>(kt + 2, nfull, nk);
               auto st_next = [&]() {
