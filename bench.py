@@ -203,7 +203,7 @@ def main():
     energy = float(sweeps["split_bf16"].energy[0].item())
     e32 = float(sweeps["fp32"].energy[0].item())
 
-    hflops, head = headline(torch, tn, max(a.steps, 10), 3)
+    hflops, head = headline(torch, tn, max(a.steps, 50), 10)
     x6 = head["split_bf16"]
     achieved = x6["tflops"]
     traffic = traffic_for("gemm_split_bf16_chi1024")

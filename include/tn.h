@@ -178,6 +178,11 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
  * is requested).  energy2 (DEVICE, 2 doubles, nullable): [L_N, R_0].
  * which: bit 0 = left sweep, bit 1 = right sweep.
  * Each site is three steps: ket-site GEMM, MPO step, bra-site GEMM.
+ * With both bits set the right sweep runs on a second stream that the
+ * library owns (one per device, default priority), forked from `stream`
+ * by an event before its first launch and joined back into `stream`
+ * after its last, so all work stays ordered after earlier and before
+ * later work on `stream` and the call can be captured in a graph.
  * ------------------------------------------------------------------- */
 int32_t tn_mps_env_sweep_workspace(int32_t n_sites, const tn_tensor* psi, const tn_tensor* mpo,
                                    size_t* bytes);

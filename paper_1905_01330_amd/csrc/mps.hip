@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -318,7 +319,7 @@ static unsigned grid_for(int64_t n) {
 }
 
 struct EnvLayout {
-  size_t t1, t2, lbuf0, lbuf1, rbuf0, rbuf1, total;
+  size_t t1, t2, t1r, t2r, lbuf0, lbuf1, rbuf0, rbuf1, total;
 };
 
 static EnvLayout env_layout(int32_t n, const std::vector<int64_t>& dims, const std::vector<int64_t>& w, int64_t d) {
@@ -329,14 +330,31 @@ static EnvLayout env_layout(int32_t n, const std::vector<int64_t>& dims, const s
   }
   for (int k = 0; k <= n; ++k) me = std::max(me, dims[k] * w[k] * dims[k]);
   EnvLayout L;
+  // each direction has its own intermediates (the two sweeps may run concurrently)
   L.t1 = 0;
   L.t2 = align256(mt * 4);
-  L.lbuf0 = L.t2 + align256(mt * 4);
+  L.t1r = L.t2 + align256(mt * 4);
+  L.t2r = L.t1r + align256(mt * 4);
+  L.lbuf0 = L.t2r + align256(mt * 4);
   L.lbuf1 = L.lbuf0 + align256(me * 4);
   L.rbuf0 = L.lbuf1 + align256(me * 4);
   L.rbuf1 = L.rbuf0 + align256(me * 4);
   L.total = L.rbuf1 + align256(me * 4);
   return L;
+}
+
+// A second stream per device (default priority) on which the right sweep
+// runs beside the left one; created on first use and kept for the process.
+static int32_t side_stream(hipStream_t& out) {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  int dev = 0;
+  TN_TRY(hip_check(hipGetDevice(&dev), "get device"));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev]) TN_TRY(hip_check(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking), "create stream"));
+  out = streams[dev];
+  return TN_OK;
 }
 
 static int32_t check_mpo(int32_t n, const tn_tensor* mpo, int64_t d, std::vector<int64_t>& w) {
@@ -458,68 +476,101 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
   char* ws = static_cast<char*>(workspace);
   float* t1 = reinterpret_cast<float*>(ws + L.t1);
   float* t2 = reinterpret_cast<float*>(ws + L.t2);
+  float* t1r = reinterpret_cast<float*>(ws + L.t1r);
+  float* t2r = reinterpret_cast<float*>(ws + L.t2r);
   float* buf[2] = {reinterpret_cast<float*>(ws + L.lbuf0), reinterpret_cast<float*>(ws + L.lbuf1)};
   float* rbuf[2] = {reinterpret_cast<float*>(ws + L.rbuf0), reinterpret_cast<float*>(ws + L.rbuf1)};
-  const float* l_last = nullptr;
-  const float* r_first = nullptr;
 
-  if (which & 1) {
-    tn_tensor cur = L_out ? L_out[0] : make_view(buf[0], TN_F32, {1, 1, 1});
-    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, st, static_cast<float*>(cur.data));
-    for (int k = 0; k < n_sites; ++k) {
-      const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
-      tn_tensor T1 = make_view(t1, TN_F32, {da, wl, d, db});
-      tn_tensor T2 = make_view(t2, TN_F32, {da, d, wr, db});
-      tn_tensor nxt = L_out ? L_out[k + 1] : make_view(buf[(k + 1) & 1], TN_F32, {db, wr, db});
-      GemmDesc g;
-      const int32_t a1[1] = {2}, b1[1] = {0};
-      TN_TRY(plan_gemm(cur, psi[k], 1, a1, b1, T1, g));
-      TN_TRY(launch_gemm(g, prec, st));
-      const tn_tensor& W = mpo[k];
-      if (WstepLeftFn f = wstep_left_fn((int)wl, (int)wr, (int)d, db, t1, t2))
-        hipLaunchKernelGGL(f, dim3((unsigned)((db / 4 + 255) / 256), (unsigned)da), dim3(256), 0, st, t1, t2,
-                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)db);
-      else
-        hipLaunchKernelGGL(wstep_left_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
-                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
-                           (int)db, (int)wl, (int)wr, (int)d);
-      TN_TRY(hip_check(hipGetLastError(), "wstep left"));
-      const int32_t a3[2] = {0, 1}, b3[2] = {0, 1};
-      TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
-      TN_TRY(launch_gemm(g, prec, st));
-      cur = nxt;
+  // left site k: L_k -> T1 -> (MPO step) T2 -> L_{k+1}
+  auto left_site = [&](int k, tn_tensor& cur, hipStream_t s) -> int32_t {
+    const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
+    tn_tensor T1 = make_view(t1, TN_F32, {da, wl, d, db});
+    tn_tensor T2 = make_view(t2, TN_F32, {da, d, wr, db});
+    tn_tensor nxt = L_out ? L_out[k + 1] : make_view(buf[(k + 1) & 1], TN_F32, {db, wr, db});
+    GemmDesc g;
+    const int32_t a1[1] = {2}, b1[1] = {0};
+    TN_TRY(plan_gemm(cur, psi[k], 1, a1, b1, T1, g));
+    TN_TRY(launch_gemm(g, prec, s));
+    const tn_tensor& W = mpo[k];
+    if (WstepLeftFn f = wstep_left_fn((int)wl, (int)wr, (int)d, db, t1, t2))
+      hipLaunchKernelGGL(f, dim3((unsigned)((db / 4 + 255) / 256), (unsigned)da), dim3(256), 0, s, t1, t2,
+                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)db);
+    else
+      hipLaunchKernelGGL(wstep_left_kernel, dim3(grid_for(da * db)), dim3(256), 0, s, t1, t2,
+                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                         (int)db, (int)wl, (int)wr, (int)d);
+    TN_TRY(hip_check(hipGetLastError(), "wstep left"));
+    const int32_t a3[2] = {0, 1}, b3[2] = {0, 1};
+    TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
+    TN_TRY(launch_gemm(g, prec, s));
+    cur = nxt;
+    return TN_OK;
+  };
+  // right site k: R_{k+1} -> T1' -> (MPO step) T2' -> R_k
+  auto right_site = [&](int k, tn_tensor& cur, hipStream_t s) -> int32_t {
+    const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
+    tn_tensor T1 = make_view(t1r, TN_F32, {da, d, db, wr});
+    tn_tensor T2 = make_view(t2r, TN_F32, {wl, da, d, db});
+    tn_tensor nxt = R_out ? R_out[k] : make_view(rbuf[k & 1], TN_F32, {da, wl, da});
+    GemmDesc g;
+    const int32_t a1[1] = {2}, b1[1] = {2};
+    TN_TRY(plan_gemm(psi[k], cur, 1, a1, b1, T1, g));
+    TN_TRY(launch_gemm(g, prec, s));
+    const tn_tensor& W = mpo[k];
+    if (WstepRightFn f = wstep_right_fn((int)wl, (int)wr, (int)d, db, t1r, t2r))
+      hipLaunchKernelGGL(f, dim3((unsigned)((db / 4 + 255) / 256), (unsigned)da), dim3(256), 0, s, t1r, t2r,
+                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                         (int)db);
+    else
+      hipLaunchKernelGGL(wstep_right_kernel, dim3(grid_for(da * db)), dim3(256), 0, s, t1r, t2r,
+                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                         (int)db, (int)wl, (int)wr, (int)d);
+    TN_TRY(hip_check(hipGetLastError(), "wstep right"));
+    const int32_t a3[2] = {1, 2}, b3[2] = {2, 3};
+    TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
+    TN_TRY(launch_gemm(g, prec, s));
+    cur = nxt;
+    return TN_OK;
+  };
+
+  // Both directions: the right sweep runs on a side stream forked from and
+  // joined back into the caller's stream (capturable), and the two are
+  // issued site by site so both streams always have work queued.
+  hipStream_t rs = st;
+  hipEvent_t fork = nullptr, join = nullptr;
+  if (which == 3) {
+    TN_TRY(side_stream(rs));
+    TN_TRY(hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "create event"));
+    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+      hipEventDestroy(fork);
+      return fail(TN_ERR_DEVICE, "create event failed");
     }
-    l_last = static_cast<const float*>(cur.data);
+    hipEventRecord(fork, st);
+    hipStreamWaitEvent(rs, fork, 0);
+  }
+  tn_tensor lcur, rcur;
+  if (which & 1) {
+    lcur = L_out ? L_out[0] : make_view(buf[0], TN_F32, {1, 1, 1});
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, st, static_cast<float*>(lcur.data));
   }
   if (which & 2) {
-    tn_tensor cur = R_out ? R_out[n_sites] : make_view(rbuf[n_sites & 1], TN_F32, {1, 1, 1});
-    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, st, static_cast<float*>(cur.data));
-    for (int k = n_sites - 1; k >= 0; --k) {
-      const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
-      tn_tensor T1 = make_view(t1, TN_F32, {da, d, db, wr});
-      tn_tensor T2 = make_view(t2, TN_F32, {wl, da, d, db});
-      tn_tensor nxt = R_out ? R_out[k] : make_view(rbuf[k & 1], TN_F32, {da, wl, da});
-      GemmDesc g;
-      const int32_t a1[1] = {2}, b1[1] = {2};
-      TN_TRY(plan_gemm(psi[k], cur, 1, a1, b1, T1, g));
-      TN_TRY(launch_gemm(g, prec, st));
-      const tn_tensor& W = mpo[k];
-      if (WstepRightFn f = wstep_right_fn((int)wl, (int)wr, (int)d, db, t1, t2))
-        hipLaunchKernelGGL(f, dim3((unsigned)((db / 4 + 255) / 256), (unsigned)da), dim3(256), 0, st, t1, t2,
-                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
-                           (int)db);
-      else
-        hipLaunchKernelGGL(wstep_right_kernel, dim3(grid_for(da * db)), dim3(256), 0, st, t1, t2,
-                           static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
-                           (int)db, (int)wl, (int)wr, (int)d);
-      TN_TRY(hip_check(hipGetLastError(), "wstep right"));
-      const int32_t a3[2] = {1, 2}, b3[2] = {2, 3};
-      TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
-      TN_TRY(launch_gemm(g, prec, st));
-      cur = nxt;
-    }
-    r_first = static_cast<const float*>(cur.data);
+    rcur = R_out ? R_out[n_sites] : make_view(rbuf[n_sites & 1], TN_F32, {1, 1, 1});
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, rs, static_cast<float*>(rcur.data));
   }
+  int32_t rc = TN_OK;
+  for (int i = 0; i < n_sites && rc == TN_OK; ++i) {
+    if (which & 1) rc = left_site(i, lcur, st);
+    if (rc == TN_OK && (which & 2)) rc = right_site(n_sites - 1 - i, rcur, rs);
+  }
+  if (which == 3) {
+    hipEventRecord(join, rs);
+    hipStreamWaitEvent(st, join, 0);
+    hipEventDestroy(fork);
+    hipEventDestroy(join);
+  }
+  TN_TRY(rc);
+  const float* l_last = (which & 1) ? static_cast<const float*>(lcur.data) : nullptr;
+  const float* r_first = (which & 2) ? static_cast<const float*>(rcur.data) : nullptr;
   if (energy2) {
     hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(64), 0, st, l_last, r_first, energy2);
     TN_TRY(hip_check(hipGetLastError(), "energy"));
