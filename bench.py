@@ -11,8 +11,8 @@ per FP32 product, one FP32 accumulator); the FP32 path is timed beside it.
 The roofline object is for the dominant kernel, the split-BF16 contraction
 GEMM at the bulk-site shape (M = 5120, K = 1024, N = 2048: L_k[1024,5,1024]
 against A_k[1024,2,1024]); its duration is measured with HIP events on the
-stream it runs on, over a loop of that contraction alone (`--mode tensordot`
-runs only that loop, for profiling).  `cpu_baseline` times the FP64 oracle
+stream it runs on, over replays of a HIP graph of that contraction alone
+(`--mode tensordot` issues the same contraction eagerly, for profiling).  `cpu_baseline` times the FP64 oracle
 on a bounded sample of bulk sites of the same sweep.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode sweep|tensordot]
@@ -87,8 +87,16 @@ def time_loop(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms
 
 
-def headline(torch, tn, steps, warmup):
-    """The bulk-site contraction alone, both precisions, with sampled accuracy."""
+HEAD_REPS = 20  # contractions per recorded graph in the headline loop
+
+
+def headline(torch, tn, steps, warmup, graph=True):
+    """The bulk-site contraction alone, both precisions, with sampled accuracy.
+
+    With graph=True each timed step replays a HIP graph of HEAD_REPS
+    back-to-back contractions, so the per-launch time is the kernel's and
+    not the host's issue rate; without it the calls are issued eagerly
+    (the form the kernel-trace profile records)."""
     import numpy as np
 
     dev = torch.device("cuda:0")
@@ -104,7 +112,13 @@ def headline(torch, tn, steps, warmup):
     rows, cols = rng.integers(0, HEAD_M, 4000), rng.integers(0, HEAD_N, 4000)
     ref = np.einsum("ik,ki->i", Lh[rows], Ah[:, cols])
     for prec in ("split_bf16", "fp32"):
-        ms = time_loop(torch, lambda: tn.contract_between(L, A, [2], [0], out=out, prec=prec), steps, warmup)
+        call = lambda: tn.contract_between(L, A, [2], [0], out=out, prec=prec)  # noqa: E731
+        if graph:
+            call()  # tile choice for this shape, outside the recording
+            g = tn.Graph(lambda: [call() for _ in range(HEAD_REPS)])
+            ms = time_loop(torch, g.replay, steps, warmup) / HEAD_REPS
+        else:
+            ms = time_loop(torch, call, steps, warmup)
         got = out.reshape(HEAD_M, HEAD_N).cpu().double().numpy()[rows, cols]
         res[prec] = {
             "ms": ms,
@@ -179,7 +193,7 @@ def main():
 
     if a.mode == "tensordot":
         tn.tune_set_level(1)
-        flops, res = headline(torch, tn, a.steps, a.warmup)
+        flops, res = headline(torch, tn, a.steps, a.warmup, graph=False)
         # a plain 256 MiB device copy in the same process: the reference
         # kernel that calibrates the HBM byte counters
         src = torch.ones(64 << 20, device="cuda:0")
@@ -200,10 +214,13 @@ def main():
     ms = {}
     for p, s in sweeps.items():
         ms[p] = time_loop(torch, s.run, a.steps, a.warmup)
+    # the same sweep recorded once as a HIP graph and replayed
+    gsweep = tn.Graph(sweeps["split_bf16"].run)
+    ms_graph = time_loop(torch, gsweep.replay, a.steps, a.warmup)
     energy = float(sweeps["split_bf16"].energy[0].item())
     e32 = float(sweeps["fp32"].energy[0].item())
 
-    hflops, head = headline(torch, tn, max(a.steps, 50), 10)
+    hflops, head = headline(torch, tn, max(a.steps, 5), 2)
     x6 = head["split_bf16"]
     achieved = x6["tflops"]
     traffic = traffic_for("gemm_split_bf16_chi1024")
@@ -249,6 +266,7 @@ def main():
         "headline_rel_err": {"split_bf16": x6["rel_err_sampled"], "fp32": head["fp32"]["rel_err_sampled"]},
         "energy": {"split_bf16": energy, "fp32": e32},
         "flops_per_step": flops,
+        "graph_replay": {"value": round(flops / (ms_graph * 1e-3) / 1e12, 3), "ms_per_step": round(ms_graph, 4)},
     }
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inputs)

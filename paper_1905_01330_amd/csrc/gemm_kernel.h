@@ -371,24 +371,28 @@ struct FastLoader {
     return (EXACT || idx < NMB) ? idx : idx % NMB;
   }
 
+  // slot v of the stage starting at k0 into register set SET
+  template <bool TAIL, int SET>
+  __device__ __forceinline__ void load_slot(int k0, int v) {
+    if constexpr (MODE == LOAD_KVEC) {
+      f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+      if (!TAIL || k0 + kq[v] < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v]);
+      st[SET][v] = x;
+    } else {
+#pragma unroll
+      for (int j = 0; j < KD; ++j) {
+        f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+        if (!TAIL || k0 + kq[v] + j < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v] + j * sk);
+        st[SET][KD * v + j] = x;
+      }
+    }
+    ptr[v] += BK * sk;
+  }
+
   template <bool TAIL, int SET>
   __device__ __forceinline__ void load(int k0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if constexpr (MODE == LOAD_KVEC) {
-        f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-        if (!TAIL || k0 + kq[v] < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v]);
-        st[SET][v] = x;
-      } else {
-#pragma unroll
-        for (int j = 0; j < KD; ++j) {
-          f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-          if (!TAIL || k0 + kq[v] + j < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v] + j * sk);
-          st[SET][KD * v + j] = x;
-        }
-      }
-      ptr[v] += BK * sk;
-    }
+    for (int v = 0; v < NV; ++v) load_slot<TAIL, SET>(k0, v);
   }
 
   // load stage kt (k0 = kt * BK) into register set SET, if the stage exists
@@ -400,27 +404,31 @@ struct FastLoader {
       load<true, SET>(kt * BK);
   }
 
+  // split slot v of register set SET and store it into the LDS stage `lds`
   template <int SET>
-  __device__ __forceinline__ void store(char* lds) {
+  __device__ __forceinline__ void store_slot(char* lds, int v) {
+    const int idx = block_of(v);
+    if constexpr (MODE == LOAD_KVEC) {
+      lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[SET][v]);
+    } else {
+      const int r0 = (idx / KQ) * 4;
+      const int kc = (idx % KQ) * KD;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int idx = block_of(v);
-      if constexpr (MODE == LOAD_KVEC) {
-        lds_put4<P, R, BK>(lds, idx / KQ, (idx % KQ) * 4, st[SET][v]);
-      } else {
-        const int r0 = (idx / KQ) * 4;
-        const int kc = (idx % KQ) * KD;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if constexpr (KD == 4) {
-            f32x4_t t = {st[SET][4 * v + 0][i], st[SET][4 * v + 1][i], st[SET][4 * v + 2][i], st[SET][4 * v + 3][i]};
-            lds_put4<P, R, BK>(lds, r0 + i, kc, t);
-          } else {
-            lds_put2<P, R, BK>(lds, r0 + i, kc, st[SET][2 * v + 0][i], st[SET][2 * v + 1][i]);
-          }
+      for (int i = 0; i < 4; ++i) {
+        if constexpr (KD == 4) {
+          f32x4_t t = {st[SET][4 * v + 0][i], st[SET][4 * v + 1][i], st[SET][4 * v + 2][i], st[SET][4 * v + 3][i]};
+          lds_put4<P, R, BK>(lds, r0 + i, kc, t);
+        } else {
+          lds_put2<P, R, BK>(lds, r0 + i, kc, st[SET][2 * v + 0][i], st[SET][2 * v + 1][i]);
         }
       }
     }
+  }
+
+  template <int SET>
+  __device__ __forceinline__ void store(char* lds) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) store_slot<SET>(lds, v);
   }
 };
 
@@ -486,6 +494,8 @@ struct GemmTile {
   // global loads run DEPTH stages ahead; workgroups of eight waves (two per
   // SIMD by construction, a fixed 256-register budget) keep one stage ahead
   static constexpr int DEPTH = NT >= 512 ? 1 : 2;
+  // parts `between` is cut into (one per 32-wide block of the wide side)
+  static constexpr int NPARTS = CHAIN ? (TM >= TN ? TM : TN) : 1;
   static constexpr int TMT = PrecInfo<P>::planes > 1 && !CHAIN ? TM : 1;
   static constexpr int TNT = PrecInfo<P>::planes > 1 && !CHAIN ? TN : 1;
 
@@ -498,22 +508,20 @@ struct GemmTile {
     }
   }
 
-  // One stage: read the operand fragments from LDS, run `between` (work
-  // independent of this stage, e.g. the next stage's LDS stores, so the
-  // scheduler can interleave it with the matrix-core ops), then the MFMAs.
+  // One stage: read the operand fragments from LDS and run the MFMAs; the
+  // callable `between(part)` (work independent of this stage: the next
+  // stage's split and LDS stores, cut into NPARTS parts) runs interleaved
+  // with the matrix-core ops.  Wide wave tiles call part b after the
+  // products of their b-th 32-wide block are issued; the others call part 0
+  // once the first fragments are read.
   struct Nothing {
-    __device__ __forceinline__ void operator()() const {}
+    __device__ __forceinline__ void operator()(int) const {}
   };
-  // LATE: `between` runs after the MFMAs (its data is still in flight when
-  // the stage starts, as with one stage of prefetch)
-  template <bool LATE = false, typename F = Nothing>
+  template <typename F = Nothing>
   __device__ static __forceinline__ void compute(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN],
                                                  f32x16_t (&tmp)[TMT][TNT], bool first, bool flush, int wm_off,
                                                  int wn_off, const F& between = F()) {
-    compute_body(sa, sb, acc, tmp, first, flush, wm_off, wn_off, [&]() {
-      if constexpr (!LATE) between();
-    });
-    if constexpr (LATE) between();
+    compute_body(sa, sb, acc, tmp, first, flush, wm_off, wn_off, between);
   }
 
   template <typename F>
@@ -536,7 +544,7 @@ struct GemmTile {
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           bfr[j] = *reinterpret_cast<const f32x4_t*>(B + (wn_off + 32 * j + lr) * LDB + kc * 8 + lh * 4);
-        if (kc == 0) between();
+        if (kc == 0) between(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -567,7 +575,7 @@ struct GemmTile {
 #pragma unroll
           for (int j = 0; j < TN; ++j) bfr[kc][j] = fb(kc, 0, j);
         }
-        between();
+        between(0);
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
@@ -585,6 +593,79 @@ struct GemmTile {
         // The fragments of the narrower side stay resident; the other side's
         // term planes are read one 32-wide block at a time.
         const f32x16_t zero = {};
+        if constexpr (CHAIN) {
+          // Wide wave tiles: each 32x32 block's term products over the whole
+          // stage form one zero-based chain, added to the accumulator at its
+          // end.  The narrower side's fragments stay resident.  Part b of
+          // `between` is issued after block b's products, so its VALU and
+          // LDS work overlaps the matrix cores.  The add is written as an FMA
+          // with an opaque 1.0 (exact: rounds t + acc once, like the add) so
+          // that the accumulator is updated in place; a plain add lets the
+          // register allocator rotate accumulators between blocks and spill.
+          float one;
+          asm("v_mov_b32 %0, 1.0" : "=v"(one));
+          if constexpr (TM >= TN) {
+            bf16x8_t bfr[NKC][NPL][TN];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+              for (int p = 0; p < NPL; ++p)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) bfr[kc][p][j] = fb(kc, p, j);
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+              f32x16_t t[TN];
+#pragma unroll
+              for (int kc = 0; kc < NKC; ++kc) {
+                bf16x8_t af[NPL];
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) af[p] = fa(kc, p, i);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                  for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+                    t[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)], bfr[kc][prod_b(P, q)][j],
+                                                                   (kc == 0 && q == 0) ? zero : t[j], 0, 0, 0);
+              }
+              between(i);
+#pragma unroll
+              for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = __builtin_fmaf(t[j][r], one, acc[i][j][r]);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          } else {
+            bf16x8_t af[NKC][NPL][TM];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+              for (int p = 0; p < NPL; ++p)
+#pragma unroll
+                for (int i = 0; i < TM; ++i) af[kc][p][i] = fa(kc, p, i);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              f32x16_t t[TM];
+#pragma unroll
+              for (int kc = 0; kc < NKC; ++kc) {
+                bf16x8_t bfr[NPL];
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) bfr[p] = fb(kc, p, j);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                  for (int q = 0; q < PrecInfo<P>::nprod; ++q)
+                    t[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kc][prod_a(P, q)][i], bfr[prod_b(P, q)],
+                                                                   (kc == 0 && q == 0) ? zero : t[i], 0, 0, 0);
+              }
+              between(j);
+#pragma unroll
+              for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = __builtin_fmaf(t[i][r], one, acc[i][j][r]);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        } else {
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
           if constexpr (TM * TN <= 4) {
@@ -596,7 +677,7 @@ struct GemmTile {
 #pragma unroll
               for (int j = 0; j < TN; ++j) bfr[p][j] = fb(kc, p, j);
             }
-            if (kc == 0) between();
+            if (kc == 0) between(0);
 #pragma unroll
             for (int q = 0; q < PrecInfo<P>::nprod; ++q)
 #pragma unroll
@@ -611,29 +692,18 @@ struct GemmTile {
             for (int p = 0; p < NPL; ++p)
 #pragma unroll
               for (int j = 0; j < TN; ++j) bfr[p][j] = fb(kc, p, j);
-            if (kc == 0) between();
+            if (kc == 0) between(0);
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
               bf16x8_t af[NPL];
 #pragma unroll
               for (int p = 0; p < NPL; ++p) af[p] = fa(kc, p, i);
-              if constexpr (CHAIN) {
 #pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                  f32x16_t t = zero;
+              for (int q = 0; q < PrecInfo<P>::nprod; ++q)
 #pragma unroll
-                  for (int q = 0; q < PrecInfo<P>::nprod; ++q)
-                    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)], bfr[prod_b(P, q)][j], t, 0, 0, 0);
-                  acc[i][j] += t;
-                }
-              } else {
-#pragma unroll
-                for (int q = 0; q < PrecInfo<P>::nprod; ++q)
-#pragma unroll
-                  for (int j = 0; j < TN; ++j)
-                    tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)], bfr[prod_b(P, q)][j],
-                                                                        (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
-              }
+                for (int j = 0; j < TN; ++j)
+                  tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)], bfr[prod_b(P, q)][j],
+                                                                      (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
             }
           } else {
             bf16x8_t af[NPL][TM];
@@ -641,33 +711,23 @@ struct GemmTile {
             for (int p = 0; p < NPL; ++p)
 #pragma unroll
               for (int i = 0; i < TM; ++i) af[p][i] = fa(kc, p, i);
-            if (kc == 0) between();
+            if (kc == 0) between(0);
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
               bf16x8_t bfr[NPL];
 #pragma unroll
               for (int p = 0; p < NPL; ++p) bfr[p] = fb(kc, p, j);
-              if constexpr (CHAIN) {
 #pragma unroll
-                for (int i = 0; i < TM; ++i) {
-                  f32x16_t t = zero;
+              for (int q = 0; q < PrecInfo<P>::nprod; ++q)
 #pragma unroll
-                  for (int q = 0; q < PrecInfo<P>::nprod; ++q)
-                    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)][i], bfr[prod_b(P, q)], t, 0, 0, 0);
-                  acc[i][j] += t;
-                }
-              } else {
-#pragma unroll
-                for (int q = 0; q < PrecInfo<P>::nprod; ++q)
-#pragma unroll
-                  for (int i = 0; i < TM; ++i)
-                    tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)][i], bfr[prod_b(P, q)],
-                                                                        (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
-              }
+                for (int i = 0; i < TM; ++i)
+                  tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(P, q)][i], bfr[prod_b(P, q)],
+                                                                      (first && kc == 0 && q == 0) ? zero : tmp[i][j], 0, 0, 0);
             }
           }
         }
         if (flush) flush_tmp(acc, tmp);
+        }
       }
     }
   }
@@ -734,10 +794,15 @@ struct GemmTile {
       la.init(d.a + bz * d.a_bs, d.gm, m0, d.M, d.gk.s[0][0], d.K);
       lb.init(d.b + bz * d.b_bs, d.gn, n0, d.N, d.gk.s[1][0], d.K);
       const int nfull = d.K / BK;
-      // Software pipeline: global loads run DEPTH stages ahead in DEPTH
-      // register sets (set = stage parity when DEPTH = 2); while stage kt's
-      // MFMAs run, stage kt+1 is split and stored into the other LDS buffer.
-      // One barrier per stage.
+      using LA = FastLoader<P, BM, BK, NT, AMODE, DEPTH>;
+      using LB = FastLoader<P, BN, BK, NT, BMODE, DEPTH>;
+      constexpr int NVA = LA::NV, NVB = LB::NV;
+      // load slots (A's, then B's) spread evenly over the parts of `between`
+      auto part_of = [](int v) { return v * NPARTS / (NVA + NVB); };
+      // Software pipeline: global loads run ahead in DEPTH register sets
+      // (set = stage parity when DEPTH = 2; with one set it is refilled right
+      // after its stage is stored); while stage kt's MFMAs run, stage kt+1
+      // is split and stored into the other LDS buffer.  One barrier per stage.
       la.template load_stage<0>(0, nfull, nk);
       lb.template load_stage<0>(0, nfull, nk);
       if constexpr (DEPTH == 2) {
@@ -746,14 +811,22 @@ struct GemmTile {
       }
       la.template store<0>(smem);
       lb.template store<0>(smem + bytesA);
+      if constexpr (DEPTH == 1) {
+        // one register set: it is refilled as soon as its stage is stored
+        la.template load_stage<0>(1, nfull, nk);
+        lb.template load_stage<0>(1, nfull, nk);
+      }
       __syncthreads();
       static_assert(FLUSH % 2 == 0 || FLUSH == 1, "stage groups must keep the register-set parity static");
       constexpr int G = FLUSH == 1 ? 2 : FLUSH;   // stages per unrolled group (even)
+      // how far ahead of the computed stage the last issued load runs
+      constexpr int AHEAD = DEPTH == 1 ? 2 : DEPTH;
       int kt0 = 0;
-      // steady state: every stage of the group loads a full stage DEPTH ahead
-      // and stores the next one, so a stage is one straight-line block that
-      // the scheduler can interleave (loads, split, LDS traffic and MFMAs)
-      for (; kt0 + G - 1 + DEPTH < nfull; kt0 += G) {
+      // steady state: every stage of the group loads a full stage AHEAD
+      // stages on and stores the next one, so a stage is one straight-line
+      // block that the scheduler can interleave (loads, split, LDS traffic
+      // and MFMAs)
+      for (; kt0 + G - 1 + AHEAD < nfull; kt0 += G) {
 #pragma unroll
         for (int s = 0; s < G; ++s) {
           const int kt = kt0 + s;
@@ -762,27 +835,49 @@ struct GemmTile {
           const bool first = FLUSH == 1 ? true : s == 0;
           const bool flush = FLUSH == 1 ? true : s == FLUSH - 1;
           if constexpr (DEPTH == 1) {
-            la.template load<false, 0>((kt + 1) * BK);
-            lb.template load<false, 0>((kt + 1) * BK);
-            auto st_next = [&]() {
-              la.template store<0>(nxt);
-              lb.template store<0>(nxt + bytesA);
+            // each slot of stage kt+1 (in registers since the same part of
+            // stage kt-1) goes to LDS, then its registers take stage kt+2:
+            // every load has a whole stage of matrix-core work to arrive
+            auto st_next = [&](int part) {
+#pragma unroll
+              for (int v = 0; v < NVA + NVB; ++v)
+                if (part_of(v) == part) {
+                  if (v < NVA) {
+                    la.template store_slot<0>(nxt, v);
+                    la.template load_slot<false, 0>((kt + 2) * BK, v);
+                  } else {
+                    lb.template store_slot<0>(nxt + bytesA, v - NVA);
+                    lb.template load_slot<false, 0>((kt + 2) * BK, v - NVA);
+                  }
+                }
             };
             compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
           } else if (s & 1) {
             la.template load<false, 1>((kt + 2) * BK);
             lb.template load<false, 1>((kt + 2) * BK);
-            auto st_next = [&]() {
-              la.template store<0>(nxt);
-              lb.template store<0>(nxt + bytesA);
+            auto st_next = [&](int part) {
+#pragma unroll
+              for (int v = 0; v < NVA + NVB; ++v)
+                if (part_of(v) == part) {
+                  if (v < NVA)
+                    la.template store_slot<0>(nxt, v);
+                  else
+                    lb.template store_slot<0>(nxt + bytesA, v - NVA);
+                }
             };
             compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
           } else {
             la.template load<false, 0>((kt + 2) * BK);
             lb.template load<false, 0>((kt + 2) * BK);
-            auto st_next = [&]() {
-              la.template store<1>(nxt);
-              lb.template store<1>(nxt + bytesA);
+            auto st_next = [&](int part) {
+#pragma unroll
+              for (int v = 0; v < NVA + NVB; ++v)
+                if (part_of(v) == part) {
+                  if (v < NVA)
+                    la.template store_slot<1>(nxt, v);
+                  else
+                    lb.template store_slot<1>(nxt + bytesA, v - NVA);
+                }
             };
             compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
           }
@@ -800,20 +895,21 @@ struct GemmTile {
             const bool first = FLUSH == 1 ? true : s == 0;
             const bool flush = FLUSH == 1 ? true : s == FLUSH - 1;
             if constexpr (DEPTH == 1) {
-              la.template load_stage<0>(kt + 1, nfull, nk);
-              lb.template load_stage<0>(kt + 1, nfull, nk);
-              auto st_next = [&]() {
+              auto st_next = [&](int part) {
+                if (part != 0) return;
                 if (kt + 1 < nk) {
                   la.template store<0>(nxt);
                   lb.template store<0>(nxt + bytesA);
                 }
+                la.template load_stage<0>(kt + 2, nfull, nk);
+                lb.template load_stage<0>(kt + 2, nfull, nk);
               };
               compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
             } else if (s & 1) {
               la.template load_stage<1>(kt + 2, nfull, nk);
               lb.template load_stage<1>(kt + 2, nfull, nk);
-              auto st_next = [&]() {
-                if (kt + 1 < nk) {
+              auto st_next = [&](int part) {
+                if (part == 0 && kt + 1 < nk) {
                   la.template store<0>(nxt);
                   lb.template store<0>(nxt + bytesA);
                 }
@@ -822,8 +918,8 @@ struct GemmTile {
             } else {
               la.template load_stage<0>(kt + 2, nfull, nk);
               lb.template load_stage<0>(kt + 2, nfull, nk);
-              auto st_next = [&]() {
-                if (kt + 1 < nk) {
+              auto st_next = [&](int part) {
+                if (part == 0 && kt + 1 < nk) {
                   la.template store<1>(nxt);
                   lb.template store<1>(nxt + bytesA);
                 }
