@@ -15,7 +15,8 @@ namespace tn {
 
 struct Cfg {
   int bm, bn, bk, wm, wn;
-  float eff;  // relative per-tile efficiency used by the heuristic
+  float eff;   // relative per-tile efficiency used by the heuristic
+  int wk = 1;  // k-slice groups of wm x wn waves
 };
 
 // eff: relative per-tile throughput measured on the bulk environment-sweep
@@ -25,6 +26,7 @@ static const Cfg kCfgs[] = {
     {128, 128, 32, 2, 2, 0.95f}, {128, 64, 32, 2, 2, 0.70f},  {64, 128, 32, 2, 2, 0.70f},
     {64, 64, 32, 2, 2, 0.55f},   {32, 32, 32, 1, 1, 0.25f},  {160, 128, 16, 1, 4, 1.00f},
     {128, 160, 16, 4, 1, 1.00f},   {160, 256, 32, 1, 8, 2.00f}, {256, 160, 32, 8, 1, 2.00f},
+    {128, 160, 32, 4, 1, 1.60f, 2}, {160, 128, 32, 1, 4, 1.60f, 2},
 };
 static constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -49,7 +51,9 @@ static int g_forced_cfg = -1;
 
 // eight-wave tiles have a fixed 256-register budget that the run-time-mode
 // gathers exceed: they serve the fast gathers only
-static bool cfg_allowed(const GemmDesc& d, int c) { return kCfgs[c].wm * kCfgs[c].wn < 8 || gemm_variant(d) != 0; }
+static bool cfg_allowed(const GemmDesc& d, int c) {
+  return kCfgs[c].wm * kCfgs[c].wn * kCfgs[c].wk < 8 || gemm_variant(d) != 0;
+}
 
 static int heuristic_cfg(const GemmDesc& d) {
   if (g_forced_cfg >= 0) return g_forced_cfg;
@@ -86,7 +90,8 @@ int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st) {
   d.tiles_n = (d.N + g.bn - 1) / g.bn;
   const int64_t tiles = (int64_t)d.tiles_m * d.tiles_n;
   if (tiles >= (1ll << 31) || d.batch > 65535) return fail(TN_ERR_UNSUPPORTED, "grid too large");
-  hipLaunchKernelGGL(pick_fn(d, prec, cfg), dim3((unsigned)tiles, 1, (unsigned)d.batch), dim3(g.wm * g.wn * 64), 0, st, d);
+  hipLaunchKernelGGL(pick_fn(d, prec, cfg), dim3((unsigned)tiles, 1, (unsigned)d.batch), dim3(g.wm * g.wn * g.wk * 64), 0,
+                     st, d);
   return hip_check(hipGetLastError(), "gemm launch");
 }
 

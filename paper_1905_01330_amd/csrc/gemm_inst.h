@@ -11,28 +11,28 @@ namespace tn {
 // allows (160 KB per CU, four SIMDs), capped at 2, and 1 when a wave's
 // accumulators (plus the split precisions' temporaries) exceed 128 registers,
 // where a smaller budget would only spill.
-template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE, int BMODE>
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE, int BMODE, int WK>
 constexpr int lds_waves_per_simd() {
-  using T = GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>;
+  using T = GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE, WK>;
   constexpr int wg = (160 * 1024) / T::lds_bytes;
-  constexpr int w = wg * WM * WN / 4;
+  constexpr int w = wg * WM * WN * WK / 4;
   constexpr int acc_regs = T::TM * T::TN * 16 + T::TMT * T::TNT * 16 * (PrecInfo<P>::planes > 1 ? 1 : 0) +
                            (T::CHAIN ? 32 : 0);
   if (acc_regs > 128) return 1;
   return w < 1 ? 1 : (w > 2 ? 2 : w);
 }
 
-template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE, int BMODE>
-__global__ void __launch_bounds__(WM* WN * 64)
-    __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd<P, BM, BN, BK, WM, WN, AMODE, BMODE>())))
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE, int BMODE, int WK = 1>
+__global__ void __launch_bounds__(WM* WN * WK * 64)
+    __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd<P, BM, BN, BK, WM, WN, AMODE, BMODE, WK>())))
         gemm_kernel(const GemmDesc d) {
-  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::lds_bytes];
+  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE, WK>::lds_bytes];
   __shared__ Group gk;
   if constexpr (AMODE < 0 || BMODE < 0) {
     copy_group(gk, d.gk);
     __syncthreads();
   }
-  GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::run(d, gk, blockIdx.x, blockIdx.z, smem);
+  GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE, WK>::run(d, gk, blockIdx.x, blockIdx.z, smem);
 }
 
 // Grouped launch: the workgroup finds its problem by binary search over the
@@ -111,6 +111,8 @@ GemmFn gemm_fn_modes(int cfg) {
     case 9: return gemm_kernel<P, 128, 160, 16, 4, 1, AM, BM_>;
     case 10: return gemm_kernel<P, 160, 256, 32, 1, 8, AM, BM_>;
     case 11: return gemm_kernel<P, 256, 160, 32, 8, 1, AM, BM_>;
+    case 12: return gemm_kernel<P, 128, 160, 32, 4, 1, AM, BM_, 2>;
+    case 13: return gemm_kernel<P, 160, 128, 32, 1, 4, AM, BM_, 2>;
     default: return gemm_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }

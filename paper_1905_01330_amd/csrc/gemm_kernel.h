@@ -473,17 +473,23 @@ __device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int& tm, i
 
 // AMODE / BMODE: LOAD_KVEC or LOAD_MNVEC select the fast gathers (single
 // merged K axis); -1 selects the run-time-mode gathers that handle any layout.
-template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE = -1, int BMODE = -1>
+// WK > 1 slices every stage's k-chunks over WK groups of WM x WN waves (each
+// group accumulates its share of K for the whole tile); the groups' sums are
+// added through LDS before the store.
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE = -1, int BMODE = -1, int WK = 1>
 struct GemmTile {
-  static constexpr int NT = WM * WN * 64;
+  static constexpr int NT = WM * WN * WK * 64;
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
   static constexpr int bytesA = LdsOperand<P, BM, BK>::bytes;
   static constexpr int bytesB = LdsOperand<P, BN, BK>::bytes;
   static constexpr int stage = bytesA + bytesB;
-  static constexpr int lds_bytes = 2 * stage;
+  // the k-slice groups' sums pass through LDS once the stages are done
+  static constexpr int red_bytes = WK > 1 ? WM * WN * (BM / WM / 32) * (BN / WN / 32) * 16 * 64 * 4 : 0;
+  static constexpr int lds_bytes = 2 * stage > red_bytes ? 2 * stage : red_bytes;
   static_assert(TM >= 1 && TN >= 1, "tile too small for 32x32 blocks");
   static_assert(BK % 16 == 0, "BK must be a multiple of 16");
+  static_assert((BK / 16) % WK == 0, "every k-slice group needs whole 16-wide chunks");
 
   // stages summed into the temporary before it is added to the accumulator (64 k)
   static constexpr int FLUSH = BK >= 64 ? 1 : 64 / BK;
@@ -520,14 +526,14 @@ struct GemmTile {
   template <typename F = Nothing>
   __device__ static __forceinline__ void compute(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN],
                                                  f32x16_t (&tmp)[TMT][TNT], bool first, bool flush, int wm_off,
-                                                 int wn_off, const F& between = F()) {
-    compute_body(sa, sb, acc, tmp, first, flush, wm_off, wn_off, between);
+                                                 int wn_off, int kslice, const F& between = F()) {
+    compute_body(sa, sb, acc, tmp, first, flush, wm_off, wn_off, kslice, between);
   }
 
   template <typename F>
   __device__ static __forceinline__ void compute_body(const char* sa, const char* sb, f32x16_t (&acc)[TM][TN],
                                                       f32x16_t (&tmp)[TMT][TNT], bool first, bool flush, int wm_off,
-                                                      int wn_off, const F& between) {
+                                                      int wn_off, int kslice, const F& between) {
     const int lane = threadIdx.x & 63;
     const int lr = lane & 31, lh = lane >> 5;
     if constexpr (!PrecInfo<P>::bf) {
@@ -536,7 +542,8 @@ struct GemmTile {
       const float* A = reinterpret_cast<const float*>(sa);
       const float* B = reinterpret_cast<const float*>(sb);
 #pragma unroll
-      for (int kc = 0; kc < BK / 8; ++kc) {
+      for (int kl = 0; kl < BK / 8 / WK; ++kl) {
+        const int kc = kslice * (BK / 8 / WK) + kl;
         f32x4_t af[TM], bfr[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -544,7 +551,7 @@ struct GemmTile {
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           bfr[j] = *reinterpret_cast<const f32x4_t*>(B + (wn_off + 32 * j + lr) * LDB + kc * 8 + lh * 4);
-        if (kc == 0) between(0);
+        if (kl == 0) between(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -559,12 +566,14 @@ struct GemmTile {
       constexpr int NPL = PrecInfo<P>::planes;
       const __bf16* A = reinterpret_cast<const __bf16*>(sa);
       const __bf16* B = reinterpret_cast<const __bf16*>(sb);
-      constexpr int NKC = BK / 16;
+      // this wave's k-chunks of the stage: kslice * NKC + [0, NKC)
+      constexpr int NKC = BK / 16 / WK;
+      const int kc0 = kslice * NKC;
       auto fa = [&](int kc, int p, int i) {
-        return *reinterpret_cast<const bf16x8_t*>(A + p * BM * LDA + bf16_slot<BK>(wm_off + 32 * i + lr, kc * 16 + lh * 8));
+        return *reinterpret_cast<const bf16x8_t*>(A + p * BM * LDA + bf16_slot<BK>(wm_off + 32 * i + lr, (kc0 + kc) * 16 + lh * 8));
       };
       auto fb = [&](int kc, int p, int j) {
-        return *reinterpret_cast<const bf16x8_t*>(B + p * BN * LDB + bf16_slot<BK>(wn_off + 32 * j + lr, kc * 16 + lh * 8));
+        return *reinterpret_cast<const bf16x8_t*>(B + p * BN * LDB + bf16_slot<BK>(wn_off + 32 * j + lr, (kc0 + kc) * 16 + lh * 8));
       };
       if constexpr (P == P_BF16) {
         bf16x8_t af[NKC][TM], bfr[NKC][TN];
@@ -737,8 +746,10 @@ struct GemmTile {
     int tm, tn;
     tile_coords(bid, d.tiles_m, d.tiles_n, tm, tn);
     const int wave = threadIdx.x >> 6;
-    const int wm_off = (wave % WM) * (BM / WM);
-    const int wn_off = (wave / WM) * (BN / WN);
+    const int wmn = wave % (WM * WN);
+    const int kslice = WK > 1 ? __builtin_amdgcn_readfirstlane(wave / (WM * WN)) : 0;
+    const int wm_off = (wmn % WM) * (BM / WM);
+    const int wn_off = (wmn / WM) * (BN / WN);
     const int m0 = tm * BM, n0 = tn * BN;
 
     float scale = 1.0f;
@@ -778,7 +789,7 @@ struct GemmTile {
               la.load((kt + 1) * BK, gk_lds);
               lb.load((kt + 1) * BK, gk_lds);
             }
-            compute(cur, cur + bytesA, acc, tmp, s == 0, s == FLUSH - 1, wm_off, wn_off);
+            compute(cur, cur + bytesA, acc, tmp, s == 0, s == FLUSH - 1, wm_off, wn_off, kslice);
             if (more) {
               la.store(nxt);
               lb.store(nxt + bytesA);
@@ -851,7 +862,7 @@ struct GemmTile {
                   }
                 }
             };
-            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
           } else if (s & 1) {
             la.template load<false, 1>((kt + 2) * BK);
             lb.template load<false, 1>((kt + 2) * BK);
@@ -865,7 +876,7 @@ struct GemmTile {
                     lb.template store_slot<0>(nxt + bytesA, v - NVA);
                 }
             };
-            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
           } else {
             la.template load<false, 0>((kt + 2) * BK);
             lb.template load<false, 0>((kt + 2) * BK);
@@ -879,7 +890,7 @@ struct GemmTile {
                     lb.template store_slot<1>(nxt + bytesA, v - NVA);
                 }
             };
-            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+            compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
           }
           __syncthreads();
         }
@@ -904,7 +915,7 @@ struct GemmTile {
                 la.template load_stage<0>(kt + 2, nfull, nk);
                 lb.template load_stage<0>(kt + 2, nfull, nk);
               };
-              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
             } else if (s & 1) {
               la.template load_stage<1>(kt + 2, nfull, nk);
               lb.template load_stage<1>(kt + 2, nfull, nk);
@@ -914,7 +925,7 @@ struct GemmTile {
                   lb.template store<0>(nxt + bytesA);
                 }
               };
-              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
             } else {
               la.template load_stage<0>(kt + 2, nfull, nk);
               lb.template load_stage<0>(kt + 2, nfull, nk);
@@ -924,13 +935,42 @@ struct GemmTile {
                   lb.template store<1>(nxt + bytesA);
                 }
               };
-              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, st_next);
+              compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
             }
             __syncthreads();
           }
         }
       }
       if (nk % FLUSH != 0) flush_tmp(acc, tmp);
+    }
+
+    if constexpr (WK > 1) {
+      // add the k-slice groups' sums into group 0 through LDS (free after
+      // the last stage): lane-contiguous rows of [wave][block][register]
+      float* red = reinterpret_cast<float*>(smem);
+      const int lane = threadIdx.x & 63;
+#pragma unroll 1
+      for (int g = 1; g < WK; ++g) {
+        __syncthreads();
+        if (kslice == g) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+              for (int r = 0; r < 16; ++r) red[((wmn * TM * TN + i * TN + j) * 16 + r) * 64 + lane] = acc[i][j][r];
+        }
+        __syncthreads();
+        if (kslice == 0) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+              for (int r = 0; r < 16; ++r) acc[i][j][r] += red[((wmn * TM * TN + i * TN + j) * 16 + r) * 64 + lane];
+        }
+      }
+      __syncthreads();
     }
 
     // epilogue.  The output offsets of the tile's BM rows and BN columns are
@@ -958,6 +998,8 @@ struct GemmTile {
     const bool mvec = d.c_mode == STORE_MVEC;
     // the operand rescale 2^-e (exact) is applied to the product instead of the A operand
     const bool scaled = scale != 1.0f;
+    // with k-slice groups only group 0 holds the sums
+    if (WK == 1 || kslice == 0) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int nl = wn_off + 32 * j + lr;
@@ -986,6 +1028,7 @@ struct GemmTile {
           }
         }
       }
+    }
     }
     if (d.c_absmax) {
 #pragma unroll
