@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["sweep", "tensordot"], default="sweep")
+    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows"], default="sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     return ap.parse_args()
 
@@ -180,6 +180,253 @@ def cpu_baseline(inputs):
     }
 
 
+# ---------------------------------------------------------------------------
+# --mode rows: every step of the path on its own, against its roofline, with
+# the oracle timed beside it on a bounded sample
+
+PEAK_ROWS = {"hbm": (8000.0, "GB/s"), "bf16": (PEAK["bf16"], "TFLOP/s"), "fp32": (PEAK["fp32"], "TFLOP/s"),
+             "fp64": (78.6, "TFLOP/s")}
+
+
+def _gtime(torch, tn, fn, reps=10, steps=3, warmup=1):
+    """ms per call of fn (launch-only calls), over replays of a graph of `reps` calls."""
+    fn()
+    torch.cuda.synchronize()
+    g = tn.Graph(lambda: [fn() for _ in range(reps)])
+    return time_loop(torch, g.replay, steps, warmup) / reps
+
+
+def _ctime(fn, min_s=1.0):
+    """seconds per call of a host (oracle) function, repeated for at least min_s."""
+    n, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s:
+            return dt / n
+
+
+def _row(rid, what, workload, work, ms, kind, cpu_work, cpu_s, sample, extra=None):
+    """work / cpu_work: bytes (kind 'hbm') or flops per call."""
+    peak, unit = PEAK_ROWS[kind]
+    scale = 1e9 if unit == "GB/s" else 1e12
+    val = work / (ms * 1e-3) / scale
+    r = {"row": rid, "what": what, "workload": workload, "ms": round(ms, 4),
+         "roofline": {"bound": "hbm" if kind == "hbm" else "mfma", "achieved": round(val, 3), "peak": peak,
+                      "unit": unit, "frac": round(val / peak, 4)},
+         "cpu_oracle": {"value": round(cpu_work / cpu_s / scale, 4), "unit": unit, "sample": sample,
+                        "seconds_per_call": round(cpu_s, 4)}}
+    if extra:
+        r.update(extra)
+    return r
+
+
+def rows(torch, tn, inputs):
+    import numpy as np
+
+    import oracle
+
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(SEED)
+    rn = lambda *shape: torch.randn(shape, device=dev, generator=gen)  # noqa: E731
+    out = []
+    tn.tune_set_level(1)
+
+    # a1-a4: the two headline tensordots of a bulk site (T1, T3 with its permuted store)
+    L = rn(CHI, W_BOND, CHI)
+    A = rn(CHI, 2, CHI) / math.sqrt(2 * CHI)
+    T2 = rn(CHI, 2, W_BOND, CHI)
+    o1 = torch.empty((CHI, W_BOND, 2, CHI), device=dev)
+    Lout = torch.empty((CHI, W_BOND, CHI), device=dev)
+    o3 = Lout.permute(1, 2, 0)     # T2 . A -> [v, b, b'] stored into L[b', v, b]
+    fl = 2.0 * HEAD_M * HEAD_K * HEAD_N
+    Lh, Ah, T2h = (x.cpu().double().numpy() for x in (L, A, T2))
+    for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
+        ms1 = _gtime(torch, tn, lambda: tn.contract_between(L, A, [2], [0], out=o1, prec=prec))
+        ms3 = _gtime(torch, tn, lambda: tn.contract_between(T2, A, [0, 1], [0, 1], out=o3, prec=prec))
+        c1 = _ctime(lambda: oracle.contract_between(Lh[:64], Ah, [(2, 0)]))
+        c3 = _ctime(lambda: oracle.contract_between(T2h, Ah[:, :, :64], [(0, 0), (1, 1)]))
+        w1 = "L[1024,5,1024] . A[1024,2,1024] over (2,0): M=5120 K=1024 N=2048"
+        w3 = "T2[1024,2,5,1024] . A[1024,2,1024] over ((0,1),(0,1)), stored permuted into L[1024,5,1024]"
+        extra = {"precision": prec}
+        if prec == "split_bf16":
+            extra["issued_mfma_frac"] = round(6 * fl / (ms1 * 1e-3) / 1e12 / PEAK["bf16"], 4)
+        out.append(_row("a1-a4 T1", "tensordot (plan, fused gather, GEMM, epilogue)", w1, fl, ms1, kind,
+                        2.0 * 64 * 5 * 1024 * 2048, c1, "first 64 rows of L", extra))
+        extra = {"precision": prec}
+        out.append(_row("a1-a4 T3", "tensordot with a permuted output", w3, fl, ms3, kind,
+                        2.0 * 64 * 2048 * 5120, c3, "first 64 columns of A", extra))
+    del L, A, T2, o1, Lout, Lh, Ah, T2h
+
+    # a5: rank-0 and rank-1 results
+    n = 1 << 28
+    x, y = rn(n), rn(n)
+    ms = _gtime(torch, tn, lambda: tn.contract_between(x, y, [0], [0]))
+    xs, ys = x[: 1 << 24].cpu().double().numpy(), y[: 1 << 24].cpu().double().numpy()
+    c = _ctime(lambda: oracle.contract_between(xs, ys, [(0, 0)]))
+    out.append(_row("a5 dot", "rank-0 result (FP64 accumulation)", "x[2^28] . y[2^28]", 8.0 * n, ms, "hbm",
+                    16.0 * (1 << 24), c, "first 2^24 elements (FP64)"))
+    del x, y
+    m = 16384
+    M_, v = rn(m, m), rn(m)
+    mv = torch.empty(m, device=dev)
+    ms = _gtime(torch, tn, lambda: tn.contract_between(M_, v, [1], [0], out=mv))
+    Ms, vs = M_[:1024].cpu().double().numpy(), v.cpu().double().numpy()
+    c = _ctime(lambda: oracle.contract_between(Ms, vs, [(1, 0)]))
+    out.append(_row("a5 matvec", "rank-1 result", "M[16384,16384] . v[16384]", 4.0 * (m * m + 2 * m), ms, "hbm",
+                    8.0 * 1024 * m, c, "first 1024 rows (FP64)"))
+    del M_, v, mv
+
+    # a6: trace edge over the two leading axes of A[64, 64, 2^18] (reads 64 contiguous rows)
+    D, X = 64, 1 << 18
+    T = rn(D, D, X)
+    tr = torch.empty(X, device=dev)
+    ms = _gtime(torch, tn, lambda: tn.trace_edge(T, 0, 1, out=tr))
+    Ts = T[:, :, : 1 << 14].cpu().double().numpy()
+    c = _ctime(lambda: oracle.trace_edge(Ts, 0, 1))
+    out.append(_row("a6", "trace edge", "A[64, 64, 2^18], trace over axes 0 and 1", 4.0 * (D * X + X), ms, "hbm",
+                    8.0 * (D * (1 << 14) + (1 << 14)), c, "A[:, :, :2^14] (FP64)"))
+    del T, tr
+
+    # a7: outer product (write-bound)
+    a, b = rn(8192), rn(32768)
+    op = torch.empty((8192, 32768), device=dev)
+    ms = _gtime(torch, tn, lambda: tn.outer_product(a, b, out=op))
+    a_s, b_s = a.cpu().double().numpy(), b[:4096].cpu().double().numpy()
+    c = _ctime(lambda: oracle.outer_product(a_s, b_s))
+    out.append(_row("a7", "outer product", "a[8192] (x) b[32768]", 4.0 * (8192 + 32768 + 8192 * 32768), ms, "hbm",
+                    8.0 * (8192 + 4096 + 8192 * 4096), c, "b[:4096] (FP64)"))
+    del a, b, op
+
+    # a8: ncon network = one environment step (L, A, W, A) with a given order
+    psi, mpo = gpu_inputs(torch, tn, inputs)
+    k = N_SITES // 2
+    Lk = rn(CHI, W_BOND, CHI) / CHI
+    tens = [Lk, psi[k], mpo[k], psi[k]]
+    labels = [[1, 2, 3], [3, 4, -3], [2, -2, 5, 4], [1, 5, -1]]
+    order = [3, 2, 4, 1, 5]
+    netout = torch.empty((CHI, W_BOND, CHI), device=dev)
+    for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
+        ms = _gtime(torch, tn, lambda: tn.contract_network(tens, labels, order=order, out=netout, prec=prec), reps=4)
+        nfl = 2.0 * (CHI * W_BOND) * CHI * (2 * CHI) + 2.0 * (CHI * CHI * 2) * (W_BOND * 2) * (W_BOND * 2) / 2 \
+            + 2.0 * CHI * (CHI * 2) * (W_BOND * CHI)
+        hs = [t.cpu().double().numpy() for t in tens]
+        hs[0], hs[3] = hs[0][:128], hs[3][:128]
+        c = _ctime(lambda: oracle.contract_network(hs, labels, order=order))
+        cfl = nfl * 128 / CHI
+        out.append(_row("a8", "ncon network driver", "L[1024,5,1024] A[1024,2,1024] W[5,5,2,2] A[1024,2,1024], "
+                        "order 3,2,4,1,5", nfl, ms, kind, cfl, c, "bra bond cut to 128 (FP64)", {"precision": prec}))
+
+    # a9: MPS inner product of the chi = 1024 chain with itself
+    dims = [1] + [int(t.shape[2]) for t in psi]
+    ifl = sum(4.0 * dims[i] ** 2 * dims[i + 1] + 4.0 * dims[i] * dims[i + 1] ** 2 for i in range(N_SITES))
+    small = [x.astype(np.float64) for x in inputs.random_mps(N_SITES, 2, 128, SEED)]
+    sd = [1] + [x.shape[2] for x in small]
+    sfl = sum(4.0 * sd[i] ** 2 * sd[i + 1] + 4.0 * sd[i] * sd[i + 1] ** 2 for i in range(N_SITES))
+    c = _ctime(lambda: oracle.mps_inner(small, small))
+    for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
+        ms = _gtime(torch, tn, lambda: tn.mps_inner(psi, psi, prec=prec), reps=4)
+        out.append(_row("a9", "MPS inner product", "<psi|psi>, N=64, chi=1024", ifl, ms, kind, sfl, c,
+                        "full chain at chi=128 (FP64)", {"precision": prec}))
+
+    # a10: the environment sweep (the bench step)
+    dw = [1] + [int(t.shape[1]) for t in mpo]
+    sfl10 = sweep_flops(dims, dw)
+    sw = tn.EnvSweep(psi, mpo, left=True, right=True, store=True, prec="split_bf16")
+    ms = _gtime(torch, tn, sw.run, reps=1, steps=3)
+    l = np.ones((1, 1, 1))
+    sites = [t.cpu().double().numpy() for t in psi[20:22]]
+    mp = [t.cpu().double().numpy() for t in mpo[20:22]]
+    l = np.random.default_rng(0).standard_normal((dims[20], dw[20], dims[20]))
+    c = _ctime(lambda: oracle.env_left_step(l, sites[0], mp[0]))
+    cfl = 2.0 * (dims[20] * dw[20]) * dims[20] * (2 * dims[21]) + 2.0 * dims[21] * (dims[20] * 2) * (dw[21] * dims[21])
+    out.append(_row("a10", "environment sweep, left + right", "XXZ, N=64, chi=1024, MPO bond 5", sfl10, ms, "bf16",
+                    cfl, c, "one bulk left step (FP64)", {"precision": "split_bf16"}))
+    del sw
+
+    # a12: uneven batch, the first 48 chains of the 512-chain workload
+    shapes = inputs.uneven_chain_shapes()[:32]
+    chains, bfl = [], 0.0
+    for i, (nn, chi) in enumerate(shapes):
+        p, q = inputs.uneven_chain(i, nn, chi)
+        d_ = [1] + [x.shape[2] for x in p]
+        bfl += sum(4.0 * d_[j] ** 2 * d_[j + 1] + 4.0 * d_[j] * d_[j + 1] ** 2 for j in range(nn))
+        chains.append(([torch.tensor(x, dtype=torch.float32, device=dev) for x in p],
+                       [torch.tensor(x, dtype=torch.float32, device=dev) for x in q]))
+    bi = tn.BatchedInner(chains, "fp32")
+    ms = _gtime(torch, tn, bi.run, reps=2)
+    cheap = sorted(range(len(shapes)), key=lambda i: shapes[i][0] * shapes[i][1] ** 3)[:4]
+    host = [inputs.uneven_chain(i, *shapes[i]) for i in cheap]
+    hfl = 0.0
+    for p, q in host:
+        d_ = [1] + [x.shape[2] for x in p]
+        hfl += sum(4.0 * d_[j] ** 2 * d_[j + 1] + 4.0 * d_[j] * d_[j + 1] ** 2 for j in range(len(p)))
+    c = _ctime(lambda: [oracle.mps_inner(p, q) for p, q in host])
+    out.append(_row("a12", "uneven batched inner products, one call", f"first 32 chains of the 512-chain batch "
+                    f"(N ~ U{{8..256}}, chi ~ U{{8..512}})", bfl, ms, "fp32", hfl, c, "the 4 cheapest of the 32 chains (FP64)"))
+    del bi, chains
+
+    # a11, a13: classifier forward (cfg4a) and training step (cfg5)
+    for tag, (n_, chi, B, seed) in (("cfg4a", (784, 64, 4096, 401)), ("cfg5", (784, 128, 1024, 501))):
+        c_ = n_ // 2
+        sites = [torch.tensor(s, dtype=torch.float32, device=dev) for s in inputs.classifier_sites(n_, chi, 10, c_, seed)]
+        pix = torch.tensor(inputs.images(B, n_, seed + 1), dtype=torch.float32, device=dev)
+        lab = torch.tensor(inputs.labels(B, 10, seed + 2), device=dev)
+        model = tn.MPSClassifier(n_, c_, 10, chi, B, ckpt_every=28, prec="split_bf16")
+        ffl = 2.0 * B * (2 * chi) * chi * (n_ - 1) + 2.0 * B * (2 * chi) * (10 * chi)
+        hs = [s.cpu().double().numpy() for s in sites]
+        hp = pix[:4].cpu().double().numpy()
+        c = _ctime(lambda: oracle.classifier_forward(hs, c_, hp))
+        ms = _gtime(torch, tn, lambda: model.forward(sites, pix), reps=2)
+        out.append(_row("a11", "classifier forward", f"{tag}: N=784, chi={chi}, batch {B}", ffl, ms, "fp64",
+                        ffl * 4 / B, c, "4 samples (FP64)", {"note": "chains on FP64 matrix cores"}))
+        if tag == "cfg5":
+            logits = model.forward(sites, pix)
+            _, dlog = tn.softmax_xent(logits, lab)
+            dsites = [torch.empty_like(s) for s in sites]
+
+            def step():
+                model.forward(sites, pix, logits)
+                model.backward(sites, pix, dlog, dsites)
+
+            ms = _gtime(torch, tn, step, reps=1)
+            c = _ctime(lambda: oracle.classifier_loss_and_grad(hs, c_, hp, lab[:4].cpu().numpy()))
+            out.append(_row("a13", "classifier training step (forward + adjoint + weight gradients)",
+                            f"{tag}: N=784, chi={chi}, batch {B}, checkpoints every 28 sites", 3 * ffl, ms, "fp64",
+                            3 * ffl * 4 / B, c, "4 samples (FP64)",
+                            {"note": "algorithmic = 3 x forward; the checkpoint recompute is extra work"}))
+        del model, sites, pix
+
+    # a14: FP64 Householder canonicalisation of the chi = 1024 chain
+    raw = [torch.tensor(x, device=dev) for x in inputs.random_mps(N_SITES, 2, CHI, SEED)]
+    qfl = 0.0
+    for i in range(N_SITES):
+        mm, nn_ = dims[i] * 2, dims[i + 1]
+        qfl += 4.0 * mm * nn_ * nn_ - 4.0 * nn_ ** 3 / 3 + (2.0 * nn_ * nn_ * 2 * dims[i + 2] if i + 1 < N_SITES else 0)
+    work = [x.clone() for x in raw]
+
+    def canon():
+        for w_, r_ in zip(work, raw):
+            w_.copy_(r_)
+        tn.mps_left_canonicalize(work)
+
+    canon()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    canon()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    hs = [x.astype(np.float64) for x in inputs.random_mps(N_SITES, 2, 128, SEED)]
+    d2 = [1] + [x.shape[2] for x in hs]
+    hfl = sum(4.0 * d2[i] * 2 * d2[i + 1] ** 2 - 4.0 * d2[i + 1] ** 3 / 3 for i in range(N_SITES))
+    c = _ctime(lambda: oracle.left_canonicalize(hs))
+    out.append(_row("a14", "FP64 Householder canonicalisation (support)", "N=64, chi=1024 random MPS", qfl, ms,
+                    "fp64", hfl, c, "full chain at chi=128 (LAPACK QR, FP64)",
+                    {"note": "host-timed (includes the copy of the raw chain)"}))
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -191,6 +438,18 @@ def main():
     import paper_1905_01330_amd as tn
     from paper_1905_01330_amd import inputs
 
+    if a.mode == "rows":
+        res = rows(torch, tn, inputs)
+        for r in res:
+            print(json.dumps(r))
+        print("| row | workload | ms | achieved | roofline | frac | oracle (sample) |")
+        print("|---|---|---|---|---|---|---|")
+        for r in res:
+            f, o = r["roofline"], r["cpu_oracle"]
+            p = f" ({r['precision']})" if "precision" in r else ""
+            print(f"| {r['row']}{p} | {r['workload']} | {r['ms']:.3f} | {f['achieved']:.3g} {f['unit']} | "
+                  f"{f['bound']} {f['peak']:g} | {f['frac']:.4f} | {o['value']:.3g} {o['unit']} ({o['sample']}) |")
+        return
     if a.mode == "tensordot":
         tn.tune_set_level(1)
         flops, res = headline(torch, tn, a.steps, a.warmup, graph=False)

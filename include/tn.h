@@ -91,12 +91,20 @@ const char* tn_version(void);
  * that exactly.  out->stride may be any permutation view, which is how a
  * final reorder_edges is fused into the store.  n_pairs == 0 is an outer
  * product.  a, b, out: TN_F32, and `out` may not overlap `a` or `b`.
- * Rank-0 and rank-1 results use wavefront reductions; the rest is a tiled
- * matrix-core GEMM whose operand gathers perform the index permutation.
+ * Rank-0 and rank-1 results use wavefront reductions (FP64 sums); the rest
+ * is a tiled matrix-core GEMM whose operand gathers perform the index
+ * permutation.
+ * workspace (DEVICE, caller-owned, nullable): scratch for results with few
+ * long sums (a dot product, a matrix-vector product with few rows): with at
+ * least TN_REDUCE_WORKSPACE_BYTES the k range of each sum is cut over many
+ * workgroups whose partials are added in a fixed order (deterministic);
+ * with NULL / 0 bytes such a sum runs on one workgroup (same result, slower).
+ * Calls that share one workspace must not overlap in time.
  * ------------------------------------------------------------------- */
+#define TN_REDUCE_WORKSPACE_BYTES 32768
 int32_t tn_contract_between(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs,
                             const int32_t* axes_a, const int32_t* axes_b, tn_tensor* out,
-                            int32_t prec, void* stream);
+                            void* workspace, size_t ws_bytes, int32_t prec, void* stream);
 
 /* Trace edge (III.A "Trace Edges"; the trace of Fig. 2):
  * out[rest] = sum_i a[.. i .. i ..] over axis1 and axis2 (equal dims),
@@ -117,7 +125,8 @@ int32_t tn_outer_product(const tn_tensor* a, const tn_tensor* b, tn_tensor* out,
  * Contracting a label between two nodes contracts every edge they share
  * (flattening).  Nodes still unconnected at the end are joined by outer
  * products in node order.  The final permutation is fused into the last
- * step's store.  Intermediates live in `workspace` (FP32, caller-owned);
+ * step's store.  Intermediates, and the scratch of the rank-0/1 sums (see
+ * tn_contract_between), live in `workspace` (caller-owned);
  * tn_contract_network_workspace returns the bytes needed.
  * ------------------------------------------------------------------- */
 int32_t tn_contract_network_workspace(int32_t n_nodes, const tn_tensor* nodes,

@@ -40,6 +40,8 @@ class TNError(RuntimeError):
 _lib = None
 
 P = C.c_void_p
+# bytes of scratch that enable the split rank-0/1 sums (TN_REDUCE_WORKSPACE_BYTES)
+REDUCE_WORKSPACE_BYTES = 32768
 I32 = C.c_int32
 SZ = C.c_size_t
 TP = C.POINTER(TnTensor)
@@ -49,7 +51,7 @@ _PROTOS = {
     "tn_status_string": (C.c_char_p, [I32]),
     "tn_last_error": (C.c_char_p, []),
     "tn_version": (C.c_char_p, []),
-    "tn_contract_between": (I32, [TP, TP, I32, I32P, I32P, TP, I32, P]),
+    "tn_contract_between": (I32, [TP, TP, I32, I32P, I32P, TP, P, SZ, I32, P]),
     "tn_trace_edge": (I32, [TP, I32, I32, TP, P]),
     "tn_outer_product": (I32, [TP, TP, TP, P]),
     "tn_contract_network_workspace": (I32, [I32, TP, I32P, I32P, I32, I32P, C.POINTER(SZ)]),

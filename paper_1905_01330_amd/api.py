@@ -37,8 +37,12 @@ def contract_between(a, b, axes_a, axes_b, out=None, prec="fp32"):
                 [b.shape[j] for j in range(b.dim()) if j not in axes_b]
         out = torch.empty(shape, dtype=torch.float32, device=a.device)
     da, db, do = L.tensor_desc(a), L.tensor_desc(b), L.tensor_desc(out)
+    # few outputs may be long sums, which split over workgroups with a small scratch
+    ws = _workspace(L.REDUCE_WORKSPACE_BYTES, a.device) if out.numel() < 1024 else None
     L.check(L.lib().tn_contract_between(C.byref(da), C.byref(db), len(axes_a), L.int_array(axes_a),
-                                        L.int_array(axes_b), C.byref(do), L.prec_code(prec), L.stream_ptr()))
+                                        L.int_array(axes_b), C.byref(do),
+                                        C.c_void_p(ws.data_ptr()) if ws is not None else None,
+                                        ws.numel() if ws is not None else 0, L.prec_code(prec), L.stream_ptr()))
     return out
 
 

@@ -720,7 +720,7 @@ int32_t label_t(const Geometry& g, const tn_tensor& ac, const float* x, float* t
   tn_tensor xv = make_view(const_cast<float*>(x), TN_F32, {g.B, g.chi, 2});
   tn_tensor tv = make_view(t, TN_F32, {g.B, g.L, g.chi});
   const int32_t pa[2] = {1, 2}, pb[2] = {0, 1};
-  return contract_between_impl(&xv, &ac, 2, pa, pb, &tv, prec, st);
+  return contract_between_impl(&xv, &ac, 2, pa, pb, &tv, nullptr, 0, prec, st);
 }
 
 // cumulative left/right forward: fills checkpoints, returns v_c and u_{c+1} blocks
@@ -898,7 +898,7 @@ int32_t tn_mps_classifier_backward(int32_t n_sites, int32_t label_site, int32_t 
     tn_tensor xv = make_view(xbuf, TN_F32, {B, chi, 2});
     tn_tensor gv = make_view(gubuf, TN_F32, {B, n_labels, chi});
     const int32_t pa[1] = {0}, pb[1] = {0};
-    TN_TRY(contract_between_impl(&xv, &gv, 1, pa, pb, &dsites[label_site], prec, st));
+    TN_TRY(contract_between_impl(&xv, &gv, 1, pa, pb, &dsites[label_site], nullptr, 0, prec, st));
   }
   // abar_c[b, a] = sum_s Phi_s sum_{l z} A_c[a, s, l, z] g[b, l] u[b, z]   (exponent e_u)
   hipLaunchKernelGGL(gu_kernel, dim3(blocks_of((int64_t)B * n_labels * chi)), dim3(256), 0, st, gl, gs0, gs1, uc,
@@ -907,7 +907,7 @@ int32_t tn_mps_classifier_backward(int32_t n_sites, int32_t label_site, int32_t 
     tn_tensor gv = make_view(gubuf, TN_F32, {B, n_labels, chi});
     tn_tensor yv = make_view(ybuf, TN_F32, {B, chi, 2});
     const int32_t pa[2] = {1, 2}, pb[2] = {2, 3};
-    TN_TRY(contract_between_impl(&gv, &ac, 2, pa, pb, &yv, prec, st));
+    TN_TRY(contract_between_impl(&gv, &ac, 2, pa, pb, &yv, nullptr, 0, prec, st));
   }
   hipLaunchKernelGGL(phi_contract_kernel, dim3(blocks_of((int64_t)B * pc)), dim3(256), 0, st, ybuf, px, n_sites,
                      label_site, B, chi, pc, uc, abar);

@@ -34,9 +34,13 @@ struct AxisSpec {
   int64_t s[3];
 };
 void build_group(std::vector<AxisSpec> axes, int primary, int n_strides, Group& g);
-int32_t launch_reduce(ReduceDesc& d, hipStream_t st);
+// scratch: nullable device buffer of scratch_bytes (TN_REDUCE_WORKSPACE_BYTES
+// enables the split reduction of few long sums)
+constexpr size_t kReduceScratchBytes = TN_REDUCE_WORKSPACE_BYTES;
+int32_t launch_reduce(ReduceDesc& d, void* scratch, size_t scratch_bytes, hipStream_t st);
 int32_t reduce_from_axes(const float* x, const float* y, float* out, const std::vector<AxisSpec>& r_axes,
-                         const std::vector<AxisSpec>& k_axes, bool bf16_round, hipStream_t st);
+                         const std::vector<AxisSpec>& k_axes, bool bf16_round, void* scratch, size_t scratch_bytes,
+                         hipStream_t st);
 
 // ---- GEMM launch -----------------------------------------------------------
 int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st);
@@ -60,6 +64,7 @@ int grouped_tile_n(int cfg);
 
 // ---- contraction entry used by the network driver -----------------------------
 int32_t contract_between_impl(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs, const int32_t* axes_a,
-                              const int32_t* axes_b, tn_tensor* out, int32_t prec, hipStream_t st);
+                              const int32_t* axes_b, tn_tensor* out, void* scratch, size_t scratch_bytes,
+                              int32_t prec, hipStream_t st);
 
 }  // namespace tn

@@ -34,6 +34,7 @@ struct Plan {
   std::vector<Node> nodes;
   std::vector<Step> steps;
   size_t ws_bytes = 0;
+  size_t scratch_off = 0;   // reduction scratch: byte offset in the workspace
   int final_node = -1;
 };
 
@@ -207,7 +208,9 @@ int32_t build_plan(int32_t n_nodes, const tn_tensor* nodes, const int32_t* label
     n.ws_off = off;
     off += align256((size_t)cnt * 4);
   }
-  plan.ws_bytes = off;
+  // then the scratch of the split reductions (few long sums)
+  plan.scratch_off = off;
+  plan.ws_bytes = off + kReduceScratchBytes;
   return TN_OK;
 }
 
@@ -258,6 +261,7 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
     if (overlaps(*out, wsv)) return fail(TN_ERR_ALIASING, "out overlaps the workspace");
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  void* scratch = static_cast<char*>(workspace) + plan.scratch_off;
   auto view_of = [&](int id) -> tn_tensor {
     const Node& n = plan.nodes[id];
     if (id == plan.final_node) return fview;
@@ -271,14 +275,16 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
       TN_TRY(tn_trace_edge(&x, s.ax[0], s.ax[1], &r, stream));
     } else if (s.kind == STEP_CONTRACT) {
       tn_tensor y = view_of(s.y);
-      TN_TRY(contract_between_impl(&x, &y, (int32_t)s.ax.size(), s.ax.data(), s.bx.data(), &r, prec, st));
+      TN_TRY(contract_between_impl(&x, &y, (int32_t)s.ax.size(), s.ax.data(), s.bx.data(), &r, scratch,
+                                   kReduceScratchBytes, prec, st));
     } else if (s.kind == STEP_OUTER) {
       tn_tensor y = view_of(s.y);
-      TN_TRY(contract_between_impl(&x, &y, 0, nullptr, nullptr, &r, prec, st));
+      TN_TRY(contract_between_impl(&x, &y, 0, nullptr, nullptr, &r, nullptr, 0, prec, st));
     } else {
       std::vector<AxisSpec> ra, ka;
       for (int a = 0; a < x.rank; ++a) ra.push_back({x.shape[a], {x.stride[a], 0, r.stride[a]}});
-      TN_TRY(reduce_from_axes(static_cast<const float*>(x.data), nullptr, static_cast<float*>(r.data), ra, ka, false, st));
+      TN_TRY(reduce_from_axes(static_cast<const float*>(x.data), nullptr, static_cast<float*>(r.data), ra, ka, false,
+                              nullptr, 0, st));
     }
   }
   return TN_OK;

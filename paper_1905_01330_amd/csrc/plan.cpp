@@ -247,7 +247,8 @@ static int32_t check_prec(int32_t prec) {
 }
 
 int32_t contract_between_impl(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs, const int32_t* axes_a,
-                              const int32_t* axes_b, tn_tensor* out, int32_t prec, hipStream_t st) {
+                              const int32_t* axes_b, tn_tensor* out, void* scratch, size_t scratch_bytes,
+                              int32_t prec, hipStream_t st) {
   TN_TRY(check_tensor(a, "a", TN_F32));
   TN_TRY(check_tensor(b, "b", TN_F32));
   TN_TRY(check_tensor(out, "out", TN_F32));
@@ -286,13 +287,14 @@ int32_t contract_between_impl(const tn_tensor* a, const tn_tensor* b, int32_t n_
     for (int i = 0; i < d.gm.n; ++i) ra.push_back({d.gm.dim[i], {d.gm.s[0][i], 0, d.gm.s[1][i]}});
     for (int i = 0; i < d.gn.n; ++i) ra.push_back({d.gn.dim[i], {0, d.gn.s[0][i], d.gn.s[1][i]}});
     for (int i = 0; i < d.gk.n; ++i) ka.push_back({d.gk.dim[i], {d.gk.s[0][i], d.gk.s[1][i], 0}});
-    return reduce_from_axes(d.a, d.b, d.c, ra, ka, prec == TN_PREC_BF16, st);
+    return reduce_from_axes(d.a, d.b, d.c, ra, ka, prec == TN_PREC_BF16, scratch, scratch_bytes, st);
   }
   return launch_gemm(d, prec, st);
 }
 
 int32_t reduce_from_axes(const float* x, const float* y, float* out, const std::vector<AxisSpec>& r_axes,
-                         const std::vector<AxisSpec>& k_axes, bool bf16_round, hipStream_t st) {
+                         const std::vector<AxisSpec>& k_axes, bool bf16_round, void* scratch, size_t scratch_bytes,
+                         hipStream_t st) {
   ReduceDesc r;
   std::memset(&r, 0, sizeof(r));
   r.x = x;
@@ -304,7 +306,7 @@ int32_t reduce_from_axes(const float* x, const float* y, float* out, const std::
   r.R = group_size(r.gr);
   r.K = group_size(r.gk);
   r.bf16_round = bf16_round ? 1 : 0;
-  return launch_reduce(r, st);
+  return launch_reduce(r, scratch, scratch_bytes, st);
 }
 
 }  // namespace tn
@@ -331,9 +333,12 @@ const char* tn_last_error(void) { return g_err; }
 const char* tn_version(void) { return "tn-mi355x 0.1 gfx950"; }
 
 int32_t tn_contract_between(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs, const int32_t* axes_a,
-                            const int32_t* axes_b, tn_tensor* out, int32_t prec, void* stream) {
+                            const int32_t* axes_b, tn_tensor* out, void* workspace, size_t ws_bytes, int32_t prec,
+                            void* stream) {
   g_err[0] = 0;
-  return contract_between_impl(a, b, n_pairs, axes_a, axes_b, out, prec, static_cast<hipStream_t>(stream));
+  if (ws_bytes > 0 && !workspace) return fail(TN_ERR_INVALID_ARGUMENT, "workspace is NULL but ws_bytes = %zu", ws_bytes);
+  return contract_between_impl(a, b, n_pairs, axes_a, axes_b, out, workspace, workspace ? ws_bytes : 0, prec,
+                               static_cast<hipStream_t>(stream));
 }
 
 int32_t tn_trace_edge(const tn_tensor* a, int32_t axis1, int32_t axis2, tn_tensor* out, void* stream) {
@@ -356,12 +361,13 @@ int32_t tn_trace_edge(const tn_tensor* a, int32_t axis1, int32_t axis2, tn_tenso
   if (has_internal_overlap(*out)) return fail(TN_ERR_INVALID_ARGUMENT, "out view maps two indices to one address");
   ka.push_back({a->shape[axis1], {a->stride[axis1] + a->stride[axis2], 0, 0}});
   return reduce_from_axes(static_cast<const float*>(a->data), nullptr, static_cast<float*>(out->data), ra, ka, false,
-                          static_cast<hipStream_t>(stream));
+                          nullptr, 0, static_cast<hipStream_t>(stream));
 }
 
 int32_t tn_outer_product(const tn_tensor* a, const tn_tensor* b, tn_tensor* out, void* stream) {
   g_err[0] = 0;
-  return contract_between_impl(a, b, 0, nullptr, nullptr, out, TN_PREC_FP32, static_cast<hipStream_t>(stream));
+  return contract_between_impl(a, b, 0, nullptr, nullptr, out, nullptr, 0, TN_PREC_FP32,
+                               static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -55,7 +55,7 @@ def desc(shape, base, strides=None, dtype=L.F32):
 
 def contract(a, b, axes_a, axes_b, out, prec=0):
     return L.lib().tn_contract_between(C.byref(a), C.byref(b), len(axes_a), L.int_array(axes_a),
-                                       L.int_array(axes_b), C.byref(out), prec, None)
+                                       L.int_array(axes_b), C.byref(out), None, 0, prec, None)
 
 
 A0, B0, O0 = FAKE, FAKE + (1 << 30), FAKE + (2 << 30)
@@ -91,7 +91,10 @@ def test_contract_rejects_null_and_bad_shapes():
     lib = L.lib()
     b = desc([4, 6], B0)
     o = desc([3, 6], O0)
-    assert lib.tn_contract_between(None, C.byref(b), 0, None, None, C.byref(o), 0, None) == -1
+    assert lib.tn_contract_between(None, C.byref(b), 0, None, None, C.byref(o), None, 0, 0, None) == -1
+    # a byte count without a buffer
+    assert lib.tn_contract_between(C.byref(desc([3, 4], A0)), C.byref(desc([4, 6], B0)), 1, L.int_array([1]),
+                                   L.int_array([0]), C.byref(o), None, 64, 0, None) == -1
     assert contract(desc([3, 0], A0), desc([4, 6], B0), [], [], desc([3, 0, 4, 6], O0)) == -1
     assert contract(desc([3, 4], 0), desc([4, 6], B0), [1], [0], desc([3, 6], O0)) == -1
 
@@ -127,12 +130,13 @@ def _network(tensors, labels, order=None):
 
 
 def test_network_workspace_and_validation():
-    # chain a(2,3) - b(3,4) - c(4,5): one intermediate of 2x4 floats
+    # chain a(2,3) - b(3,4) - c(4,5): one intermediate of 2x4 floats (one
+    # 256-byte slot), then the scratch of the split rank-0/1 sums
     ts = [desc([2, 3], A0), desc([3, 4], B0), desc([4, 5], O0)]
     r, nb = _network(ts, [[-1, 0], [0, 1], [1, -2]])
-    assert r == 0 and nb == 256
+    assert r == 0 and nb == 256 + L.REDUCE_WORKSPACE_BYTES
     r, nb = _network(ts, [[-1, 0], [0, 1], [1, -2]], order=[1, 0])
-    assert r == 0 and nb == 256
+    assert r == 0 and nb == 256 + L.REDUCE_WORKSPACE_BYTES
     assert _network(ts, [[-1, 0], [0, 1], [2, -2]])[0] == -1         # label 2 appears once
     assert _network(ts, [[-1, 0], [0, -1], [1, -2]])[0] == -1        # open label repeated
     assert _network(ts, [[-1, 0], [1, 0], [1, -2]])[0] == -2         # dims 3 vs 4 on label 0 ... and 1
@@ -185,3 +189,12 @@ def test_binding_refuses_cpu_tensors():
 
     with pytest.raises(ValueError):
         tn.contract_between(torch.ones(2), torch.ones(2), [0], [0])
+
+
+def test_reduce_workspace_constant_matches_header():
+    import os
+    import re
+
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "tn.h")).read()
+    m = re.search(r"#define\s+TN_REDUCE_WORKSPACE_BYTES\s+(\d+)", hdr)
+    assert m and int(m.group(1)) == L.REDUCE_WORKSPACE_BYTES

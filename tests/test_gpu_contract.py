@@ -349,3 +349,106 @@ def test_network_single_node_permutation_and_disconnected():
     c = f32(rng.standard_normal((4, 4)))
     out = tn.contract_network([gpu(c)], [[0, 0]])
     assert abs(float(host(out)) - float(np.trace(c))) < 1e-5
+
+
+def _rounded_close(got, ref, absref, what):
+    """FP64 sums rounded once to FP32: within half an FP32 ulp of the exact
+    value plus the FP64 summation error (K * 2^-53 of the absolute sum)."""
+    got = np.asarray(got, dtype=np.float64)
+    err = np.abs(got - ref)
+    bound = 2.0 ** -24 * np.abs(ref) + 1e-9 * absref + 1e-30
+    assert np.all(err <= bound), (what, float(np.max(err / bound)))
+
+
+def _contract_raw(a, b, axes_a, axes_b, out, ws):
+    """The C entry point with an explicit workspace (None: no scratch)."""
+    import ctypes as C
+    from paper_1905_01330_amd import _lib as Lb
+
+    da, db, do = Lb.tensor_desc(a), Lb.tensor_desc(b), Lb.tensor_desc(out)
+    Lb.check(Lb.lib().tn_contract_between(C.byref(da), C.byref(db), len(axes_a), Lb.int_array(axes_a),
+                                          Lb.int_array(axes_b), C.byref(do),
+                                          C.c_void_p(ws.data_ptr()) if ws is not None else None,
+                                          ws.numel() if ws is not None else 0, 0, Lb.stream_ptr()))
+    return out
+
+
+@pytest.mark.parametrize("with_scratch", [True, False])
+def test_long_sums_split_and_fallback(with_scratch):
+    """Dot products and few-row matrix-vector products with long, ragged,
+    misaligned sums: split over workgroups (scratch) or one workgroup per
+    sum (no scratch); both give the FP64 sum rounded once, bit-identically
+    on repeated calls."""
+    rng = np.random.default_rng(21)
+    ws = torch.empty(tn._lib.REDUCE_WORKSPACE_BYTES, dtype=torch.uint8, device=DEV) if with_scratch else None
+    n = (1 << 22) + 3
+    v = f32(rng.standard_normal(n + 1))
+    w = f32(rng.standard_normal(n + 1))
+    gv, gw = gpu(v), gpu(w)
+    for off in (0, 1):   # off = 1: rows not 16-byte aligned
+        x, y = gv[off:off + n], gw[off:off + n]
+        out = torch.empty((), device=DEV)
+        _contract_raw(x, y, [0], [0], out, ws)
+        first = host(out).copy()
+        _contract_raw(x, y, [0], [0], out, ws)
+        assert np.array_equal(first, host(out)), "repeated call differs"
+        xs, ys = v[off:off + n].astype(np.float64), w[off:off + n].astype(np.float64)
+        _rounded_close(first, float(np.dot(xs, ys)), float(np.dot(np.abs(xs), np.abs(ys))), f"dot off={off}")
+    m = f32(rng.standard_normal((7, 200_003)))
+    x = f32(rng.standard_normal(200_003))
+    out = torch.empty(7, device=DEV)
+    _contract_raw(gpu(m), gpu(x), [1], [0], out, ws)
+    m64, x64 = m.astype(np.float64), x.astype(np.float64)
+    _rounded_close(host(out), m64 @ x64, np.abs(m64) @ np.abs(x64), "few-row matvec")
+
+
+def test_reduction_layout_paths():
+    """Many long rows (wavefront per row, 16-byte loads, ragged tail), column
+    sums (thread per output), traces over leading and outer axes, outer
+    products with four outputs per thread, odd extents and misaligned or
+    permuted outputs: all exact to one FP32 rounding of the FP64 sum."""
+    rng = np.random.default_rng(22)
+    m = f32(rng.standard_normal((3000, 1031)))
+    x = f32(rng.standard_normal(1031))
+    m64, x64 = m.astype(np.float64), x.astype(np.float64)
+    out = tn.contract_between(gpu(m), gpu(x), [1], [0])
+    _rounded_close(host(out), m64 @ x64, np.abs(m64) @ np.abs(x64), "matvec rows")
+    y = f32(rng.standard_normal(3000))
+    out = tn.contract_between(gpu(y), gpu(m), [0], [0])
+    y64 = y.astype(np.float64)
+    _rounded_close(host(out), y64 @ m64, np.abs(y64) @ np.abs(m64), "column sums")
+    t = f32(rng.standard_normal((8, 8, 1003)))
+    out = tn.trace_edge(gpu(t), 0, 1)
+    _rounded_close(host(out), oracle.trace_edge(t.astype(np.float64), 0, 1),
+                   oracle.trace_edge(np.abs(t).astype(np.float64), 0, 1), "trace leading axes")
+    t = f32(rng.standard_normal((6, 1001, 6)))
+    out = tn.trace_edge(gpu(t), 0, 2)
+    _rounded_close(host(out), oracle.trace_edge(t.astype(np.float64), 0, 2),
+                   oracle.trace_edge(np.abs(t).astype(np.float64), 0, 2), "trace outer axes")
+    for na, nb in ((37, 1024), (5, 1023), (3, 4)):
+        a = f32(rng.standard_normal(na))
+        b = f32(rng.standard_normal(nb))
+        ref = oracle.outer_product(a.astype(np.float64), b.astype(np.float64))
+        out = tn.outer_product(gpu(a), gpu(b))
+        np.testing.assert_array_equal(host(out), ref.astype(np.float32))
+        buf = torch.empty(na * nb + 1, device=DEV)
+        mis = buf[1:].view(na, nb)             # 4-byte aligned only
+        tn.outer_product(gpu(a), gpu(b), out=mis)
+        np.testing.assert_array_equal(host(mis), ref.astype(np.float32))
+        tr = torch.empty((nb, na), device=DEV)
+        tn.outer_product(gpu(a), gpu(b), out=tr.t())   # permuted store
+        np.testing.assert_array_equal(host(tr).T, ref.astype(np.float32))
+
+
+def test_network_ending_in_a_long_dot():
+    """A network whose last step is a long dot product takes the split sum
+    from the network workspace."""
+    rng = np.random.default_rng(23)
+    a = f32(rng.standard_normal((256, 300)))
+    b = f32(rng.standard_normal((300, 256)))
+    c = f32(rng.standard_normal((256, 256)))
+    out = tn.contract_network([gpu(a), gpu(b), gpu(c)], [[0, 1], [1, 2], [2, 0]], order=[1, 2, 0])
+    ab = a.astype(np.float64) @ b.astype(np.float64)
+    ref = float(np.sum(ab * c.astype(np.float64).T))
+    scale = float(np.sum((np.abs(a).astype(np.float64) @ np.abs(b)) * np.abs(c).T))
+    assert abs(float(host(out)) - ref) <= 1e-5 * scale
