@@ -77,7 +77,7 @@ struct ReduceDesc {
   const float* y;
   float* out;
   int64_t R, K;
-  int32_t mode;        // 0: thread per output, 1: wave per output, 2: block per output
+  int32_t mode;        // 0: thread per output, 1: wave per output, 2: block per output, 3: four outputs per thread
   int32_t bf16_round;  // round operands to BF16 before the product
   int32_t kcontig;     // k is one unit-stride axis of X (and of Y)
   Group gr, gk;

@@ -126,6 +126,7 @@ static int tune_cfg(GemmDesc& d, int32_t prec, hipStream_t st) {
 }
 
 int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
+  if (g_forced_cfg < 0 && gemm_small_fits(d)) return launch_gemm_small(d, prec, st);
   int cfg;
   int level;
   auto key = std::make_tuple(d.M, d.N, d.K, d.batch, d.a_mode, d.b_mode, d.c_mode, (int)prec,

@@ -44,6 +44,9 @@ int32_t reduce_from_axes(const float* x, const float* y, float* out, const std::
 
 // ---- GEMM launch -----------------------------------------------------------
 int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st);
+// K <= 32 with N or M <= 16 (and no batch, scale or max-abs): the HBM-bound path
+bool gemm_small_fits(const GemmDesc& d);
+int32_t launch_gemm_small(const GemmDesc& d, int32_t prec, hipStream_t st);
 int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st);
 int gemm_num_cfgs();
 

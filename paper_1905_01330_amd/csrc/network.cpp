@@ -19,7 +19,24 @@ struct Node {
   std::vector<int64_t> shape;
   int input;        // >= 0: caller's node index; -1: intermediate
   size_t ws_off;    // intermediate: byte offset in the workspace
+  std::vector<int> mem;   // intermediate: axes from outermost to innermost in memory (empty: as listed)
 };
+
+// element strides of an intermediate laid out in `mem` order
+std::vector<int64_t> mem_strides(const Node& n) {
+  const int r = (int)n.shape.size();
+  std::vector<int64_t> st(r, 1);
+  if (n.mem.empty()) {
+    for (int a = r - 2; a >= 0; --a) st[a] = st[a + 1] * n.shape[a + 1];
+    return st;
+  }
+  int64_t acc = 1;
+  for (int i = r - 1; i >= 0; --i) {
+    st[n.mem[i]] = acc;
+    acc *= n.shape[n.mem[i]];
+  }
+  return st;
+}
 
 enum StepKind { STEP_TRACE, STEP_CONTRACT, STEP_OUTER, STEP_COPY };
 
@@ -198,6 +215,41 @@ int32_t build_plan(int32_t n_nodes, const tn_tensor* nodes, const int32_t* label
     plan.steps.push_back(st);
   }
   plan.final_node = plan.steps.back().result;
+  // Memory order of the intermediates that feed a pairwise contraction: the
+  // axes contracted in that step form one block, outermost, in the order of
+  // the partner's strides (so the contracted index merges into one strided
+  // axis in both operands and the GEMM takes its fast gathers), and the
+  // other axes follow in their listed order (the producer's last free axis
+  // stays innermost, so its stores stay contiguous).  The stores of every
+  // step go through the output's strides, so any order costs nothing there.
+  auto strides_of = [&](int id) -> std::vector<int64_t> {
+    const Node& n = plan.nodes[id];
+    if (n.input >= 0) return std::vector<int64_t>(nodes[n.input].stride, nodes[n.input].stride + n.shape.size());
+    return mem_strides(n);
+  };
+  std::vector<bool> decided(plan.nodes.size(), false);
+  auto arrange = [&](int id, const std::vector<int32_t>& own, int partner, const std::vector<int32_t>& theirs) {
+    Node& n = plan.nodes[id];
+    if (n.input >= 0 || id == plan.final_node || decided[id]) return;
+    const std::vector<int64_t> ps = strides_of(partner);
+    std::vector<int> idx(own.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int p, int q) { return ps[theirs[p]] > ps[theirs[q]]; });
+    std::vector<bool> used(n.shape.size(), false);
+    n.mem.clear();
+    for (int i : idx) {
+      n.mem.push_back(own[i]);
+      used[own[i]] = true;
+    }
+    for (int a = 0; a < (int)n.shape.size(); ++a)
+      if (!used[a]) n.mem.push_back(a);
+    decided[id] = true;
+  };
+  for (auto& st : plan.steps) {
+    if (st.kind != STEP_CONTRACT) continue;
+    arrange(st.x, st.ax, st.y, st.bx);
+    arrange(st.y, st.bx, st.x, st.ax);
+  }
   // workspace for every intermediate except the final one
   size_t off = 0;
   for (auto& st : plan.steps) {
@@ -266,7 +318,11 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
     const Node& n = plan.nodes[id];
     if (id == plan.final_node) return fview;
     if (n.input >= 0) return nodes[n.input];
-    return contiguous_view(static_cast<char*>(workspace) + n.ws_off, TN_F32, (int32_t)n.shape.size(), n.shape.data());
+    tn_tensor v = contiguous_view(static_cast<char*>(workspace) + n.ws_off, TN_F32, (int32_t)n.shape.size(),
+                                  n.shape.data());
+    const std::vector<int64_t> st = mem_strides(n);
+    for (size_t a = 0; a < st.size(); ++a) v.stride[a] = st[a];
+    return v;
   };
   for (auto& s : plan.steps) {
     tn_tensor x = view_of(s.x);

@@ -9,6 +9,9 @@
 //   mode 0: one thread per output: when the outputs, not the summed index,
 //     are unit-stride in X (column sums, traces over leading axes) or the
 //     sums are short;
+//   mode 3: as mode 0, four consecutive outputs per thread with 16-byte
+//     loads, when the innermost output axis is unit-stride in X (and Y) and
+//     its extent is a multiple of four;
 //   mode 1: one 64-lane wavefront per output, lanes stride over k (16-byte
 //     loads when k is one unit-stride axis of both operands), then a
 //     butterfly reduction across the wavefront;
@@ -32,6 +35,7 @@ __device__ inline int64_t k_offset(const Group& g, int ti, uint32_t k) {
 
 __device__ inline double partial_sum(const ReduceDesc& d, int64_t ox, int64_t oy, int64_t k0, int64_t kstep) {
   double acc = 0.0;
+#pragma unroll 4
   for (int64_t k = k0; k < d.K; k += kstep) {
     float xv = d.x[ox + k_offset(d.gk, 0, (uint32_t)k)];
     float yv = d.y ? d.y[oy + k_offset(d.gk, 1, (uint32_t)k)] : 1.0f;
@@ -132,6 +136,51 @@ __global__ void __launch_bounds__(256) reduce_kernel(const ReduceDesc d) {
   }
 }
 
+// mode 3: four consecutive outputs per thread (its own kernel, so the wider
+// registers do not lower the occupancy of the other modes)
+__global__ void __launch_bounds__(256) reduce4_kernel(const ReduceDesc d) {
+  const int in = d.gr.n - 1;
+  const int64_t so = d.gr.s[2][in];
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.R / 4; q += nthreads) {
+    int64_t o[3];
+    group_offsets<3>(d.gr, (uint32_t)(4 * q), o, 0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int64_t k = 0; k < d.K; ++k) {
+      const float* xp = d.x + o[0] + k_offset(d.gk, 0, (uint32_t)k);
+      const float* yp = d.y ? d.y + o[1] + k_offset(d.gk, 1, (uint32_t)k) : nullptr;
+      f4_t xv, yv = {1.f, 1.f, 1.f, 1.f};
+      if ((reinterpret_cast<uintptr_t>(xp) & 15) == 0) {
+        xv = *reinterpret_cast<const f4_t*>(xp);
+      } else {
+        xv = f4_t{xp[0], xp[1], xp[2], xp[3]};
+      }
+      if (yp) {
+        if ((reinterpret_cast<uintptr_t>(yp) & 15) == 0)
+          yv = *reinterpret_cast<const f4_t*>(yp);
+        else
+          yv = f4_t{yp[0], yp[1], yp[2], yp[3]};
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float a = xv[j], b = yv[j];
+        if (d.bf16_round) {
+          a = bf16_rne(a);
+          b = bf16_rne(b);
+        }
+        acc[j] += (double)a * (double)b;
+      }
+    }
+    if (so == 1 && (reinterpret_cast<uintptr_t>(d.out + o[2]) & 15) == 0) {
+      *reinterpret_cast<f4_t*>(d.out + o[2]) = f4_t{(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) d.out[o[2] + j * so] = (float)acc[j];
+    }
+  }
+}
+
 // split reduction, pass 1: workgroup (g, r) sums chunk g of output r's k range
 __global__ void __launch_bounds__(256) reduce_partial_kernel(const ReduceDesc d, double* partial, int64_t chunk) {
   __shared__ double part[4];
@@ -224,7 +273,10 @@ int32_t launch_reduce(ReduceDesc& d, void* scratch, size_t scratch_bytes, hipStr
   }
   // outputs unit-stride in X and k not: one thread per output keeps the loads coalesced
   const bool r_unit = d.gr.n >= 1 && d.gr.s[0][in] == 1 && !d.kcontig;
-  if (d.K <= 16 || r_unit || (d.R >= 4096 && !d.kcontig))
+  const bool r_vec4 = r_unit && d.gr.dim[in] % 4 == 0 && (!d.y || d.gr.s[1][in] == 1);
+  if (r_vec4)
+    d.mode = 3;
+  else if (d.K <= 16 || r_unit || (d.R >= 4096 && !d.kcontig))
     d.mode = 0;
   else if (d.R >= 64)
     d.mode = 1;
@@ -233,13 +285,18 @@ int32_t launch_reduce(ReduceDesc& d, void* scratch, size_t scratch_bytes, hipStr
   int64_t blocks;
   if (d.mode == 0)
     blocks = (d.R + 255) / 256;
+  else if (d.mode == 3)
+    blocks = (d.R / 4 + 255) / 256;
   else if (d.mode == 1)
     blocks = (d.R + 3) / 4;
   else
     blocks = d.R;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d);
+  if (d.mode == 3)
+    hipLaunchKernelGGL(reduce4_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d);
+  else
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d);
   return hip_check(hipGetLastError(), "reduce launch");
 }
 

@@ -421,6 +421,11 @@ def test_reduction_layout_paths():
     out = tn.trace_edge(gpu(t), 0, 1)
     _rounded_close(host(out), oracle.trace_edge(t.astype(np.float64), 0, 1),
                    oracle.trace_edge(np.abs(t).astype(np.float64), 0, 1), "trace leading axes")
+    t = f32(rng.standard_normal((8, 8, 1024)))
+    for view in (slice(0, 1024), slice(1, 1001)):      # four outputs per thread: aligned, misaligned
+        out = tn.trace_edge(gpu(t)[:, :, view], 0, 1)
+        tv = t[:, :, view].astype(np.float64)
+        _rounded_close(host(out), oracle.trace_edge(tv, 0, 1), oracle.trace_edge(np.abs(tv), 0, 1), "trace x4")
     t = f32(rng.standard_normal((6, 1001, 6)))
     out = tn.trace_edge(gpu(t), 0, 2)
     _rounded_close(host(out), oracle.trace_edge(t.astype(np.float64), 0, 2),
@@ -452,3 +457,25 @@ def test_network_ending_in_a_long_dot():
     ref = float(np.sum(ab * c.astype(np.float64).T))
     scale = float(np.sum((np.abs(a).astype(np.float64) @ np.abs(b)) * np.abs(c).T))
     assert abs(float(host(out)) - ref) <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "bf16"])
+def test_tiny_contracted_and_free_extents(prec):
+    """An MPO acting on a bond pair (K = 10, N = 10 over a large M), its
+    transpose (M = 10), K = 32 / N = 16 at the limit, strided views and a
+    permuted output: the HBM-bound small path, against the oracle."""
+    rng = np.random.default_rng(24)
+    tol = TOL[prec]
+    t1 = f32(rng.standard_normal((64, 5, 2, 96)))        # [a', u, s, b]
+    w = f32(rng.standard_normal((5, 5, 2, 2)))           # [u, v, t, s]
+    out = tn.contract_between(gpu(t1), gpu(w), [1, 2], [0, 3], prec=prec)
+    check(host(out), oracle.tensordot(t1, w, [1, 2], [0, 3]), abs_scale(t1, w, [1, 2], [0, 3]), tol, "mpo step")
+    out = tn.contract_between(gpu(w), gpu(t1), [0, 3], [1, 2], prec=prec)
+    check(host(out), oracle.tensordot(w, t1, [0, 3], [1, 2]), abs_scale(w, t1, [0, 3], [1, 2]), tol, "transposed")
+    a = f32(rng.standard_normal((3000, 32)))
+    b = f32(rng.standard_normal((32, 16)))
+    big = gpu(np.zeros((3000, 64), dtype=np.float32))
+    big[:, ::2] = gpu(a)
+    res = torch.empty((16, 3000), device=DEV)
+    tn.contract_between(big[:, ::2], gpu(b), [1], [0], out=res.t(), prec=prec)
+    check(host(res).T, a.astype(np.float64) @ b, np.abs(a).astype(np.float64) @ np.abs(b), tol, "strided, permuted out")
