@@ -1,11 +1,18 @@
 // Left-canonical gauge of an MPS in FP64 on the GPU: successive Householder
 // QR factorisations (Golub and Van Loan, "Matrix Computations", 5.1-5.2).
 // For site k the carried triangular factor is absorbed first
-// (X = R_{k-1} A_k viewed as (D_k d) x D_{k+1}), X is factorised in place
-// column by column (one reflector kernel and one trailing-update kernel per
-// column), the thin Q is accumulated backwards from [I; 0], and signs are
-// fixed so that diag(R) >= 0.  X and Q are kept column-major so every
-// reflector and column update reads contiguous memory.
+// (X = R_{k-1} A_k viewed as (D_k d) x D_{k+1}), X is factorised in place,
+// the thin Q is accumulated backwards from [I; 0], and signs are fixed so
+// that diag(R) >= 0.  X and Q are kept column-major so every reflector and
+// column update reads contiguous memory.
+// Up to 2048 rows the factorisation is blocked in the compact WY form
+// (Schreiber and Van Loan; Golub and Van Loan 5.2.3): a panel of 16 columns
+// is factorised by one workgroup holding the panel in registers (two
+// workgroup reductions per column), which then forms the panel's triangular
+// factor T from the Gram matrix of its reflectors; one launch applies
+// I - V T^T V^T to all trailing columns (one reduction per workgroup); Q is
+// accumulated panel by panel in reverse with I - V T V^T.
+// Taller matrices take one reflector launch and one update launch per column.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -102,6 +109,314 @@ __global__ void __launch_bounds__(256) reflect_cols_kernel(const double* __restr
   for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) col[i] -= w * v[i];
 }
 
+// ---- blocked path (m <= kQrThreads * kQrRows) --------------------------------
+
+constexpr int kQrThreads = 512;   // threads per workgroup; thread t owns rows t + 512 q
+constexpr int kQrRows = 4;        // rows per thread
+constexpr int kQrNb = 16;         // panel width
+constexpr int kQrCb = 4;          // trailing columns per workgroup
+constexpr int kQrWaves = kQrThreads / 64;
+
+// Wavefront reduce-scatter of N partial values (N a power of two <= 64):
+// lane l returns the sum over the 64 lanes of value l % N.  Each halving step
+// sends one half of the remaining values to the partner lane and keeps the
+// other half (N - 1 exchanges in all, instead of 6 N for N separate sums).
+template <int N, int H>
+__device__ __forceinline__ void qr_halve(double (&v)[N], int lane) {
+  if constexpr (H >= 1) {
+    const bool up = (lane & H) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double send = up ? v[i] : v[i + H];
+      const double keep = up ? v[i + H] : v[i];
+      v[i] = keep + __shfl_xor(send, H, 64);
+    }
+    qr_halve<N, H / 2>(v, lane);
+  }
+}
+
+template <int N>
+__device__ inline double qr_reduce_scatter(double (&v)[N]) {
+  const int lane = threadIdx.x & 63;
+  qr_halve<N, N / 2>(v, lane);
+  double r = v[0];
+#pragma unroll
+  for (int mk = N; mk < 64; mk *= 2) r += __shfl_xor(r, mk, 64);
+  return r;
+}
+
+// Workgroup sum of v[0..NV) returned to every thread.  P (a power of two >=
+// NV) values per wavefront go through red[buf] (two buffers used in turn, so
+// one barrier per reduction suffices: a wavefront can only write a buffer
+// again after every wavefront has passed the barrier of the reduction that
+// read it last).
+template <int NV, int P>
+__device__ inline void qr_block_sum(double (&v)[NV], double (*red)[kQrWaves * 64], int& buf) {
+  double w[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) w[i] = i < NV ? v[i] : 0.0;
+  const double r = qr_reduce_scatter<P>(w);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane < P) red[buf][wave * P + lane] = r;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kQrWaves; ++wv) t += red[buf][wv * P + i];
+    v[i] = t;
+  }
+  buf ^= 1;
+}
+
+// the reflector of panel column J (a template argument, so the register
+// panel is only indexed by constants), then its update of the panel columns
+// to its right; the same arithmetic as reflector_kernel + reflect_cols_kernel
+template <int J>
+__device__ __forceinline__ void qr_panel_step(double (&x)[kQrRows][kQrNb], double (*red)[kQrWaves * 64], int& buf,
+                                              double* tau, int m, int j0, int nb) {
+  if constexpr (J < kQrNb) {
+    if (J < nb) {
+      const int gj = j0 + J;
+      double s[2] = {0.0, 0.0};   // sigma (rows below gj), alpha (row gj)
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) {
+        const int row = threadIdx.x + kQrThreads * q;
+        if (row > gj && row < m) s[0] += x[q][J] * x[q][J];
+        if (row == gj) s[1] = x[q][J];
+      }
+      qr_block_sum<2, 2>(s, red, buf);
+      const double sigma = s[0], alpha = s[1];
+      double t = 0.0;
+      if (sigma != 0.0) {
+        const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        const double scale = 1.0 / (alpha - beta);
+        t = (beta - alpha) / beta;
+#pragma unroll
+        for (int q = 0; q < kQrRows; ++q) {
+          const int row = threadIdx.x + kQrThreads * q;
+          if (row > gj && row < m) x[q][J] *= scale;
+          if (row == gj) x[q][J] = beta;
+        }
+      }
+      if (threadIdx.x == 0) tau[gj] = t;
+      if constexpr (J + 1 < kQrNb) {
+        if (t != 0.0 && J + 1 < nb) {
+          constexpr int NW = kQrNb - J - 1;
+          double w[NW];
+#pragma unroll
+          for (int c = 0; c < NW; ++c) {
+            w[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQrRows; ++q) {
+              const int row = threadIdx.x + kQrThreads * q;
+              if (row > gj && row < m) w[c] += x[q][J] * x[q][J + 1 + c];
+              if (row == gj) w[c] += x[q][J + 1 + c];
+            }
+          }
+          qr_block_sum<NW, (NW > 8 ? 16 : NW > 4 ? 8 : NW > 2 ? 4 : NW > 1 ? 2 : 1)>(w, red, buf);
+#pragma unroll
+          for (int c = 0; c < NW; ++c) {
+#pragma unroll
+            for (int q = 0; q < kQrRows; ++q) {
+              const int row = threadIdx.x + kQrThreads * q;
+              if (row > gj && row < m) x[q][J + 1 + c] -= t * w[c] * x[q][J];
+              if (row == gj) x[q][J + 1 + c] -= t * w[c];
+            }
+          }
+        }
+      }
+    }
+    qr_panel_step<J + 1>(x, red, buf, tau, m, j0, nb);
+  }
+}
+
+// Factorise columns j0 .. j0+nb-1 (rows j0..m-1) of the column-major X in
+// place, then form the panel's triangular factor (LAPACK larft, forward,
+// columnwise): H_0 ... H_{nb-1} = I - V T V^T with T[j][j] = tau_j and
+// T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j); T row-major 16 x 16.
+__global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(double* xc, double* tau, double* tf, int m, int j0,
+                                                              int nb) {
+  __shared__ double red[2][kQrWaves * 64];
+  __shared__ double gram[kQrNb * kQrNb];
+  __shared__ double tl[kQrNb * kQrNb];
+  int buf = 0;
+  double x[kQrRows][kQrNb];
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int row = threadIdx.x + kQrThreads * q;
+#pragma unroll
+    for (int c = 0; c < kQrNb; ++c) x[q][c] = (row < m && c < nb) ? xc[(int64_t)(j0 + c) * m + row] : 0.0;
+  }
+  qr_panel_step<0>(x, red, buf, tau, m, j0, nb);
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int row = threadIdx.x + kQrThreads * q;
+    if (row < m) {
+#pragma unroll
+      for (int c = 0; c < kQrNb; ++c)
+        if (c < nb) xc[(int64_t)(j0 + c) * m + row] = x[q][c];
+    }
+  }
+  // Gram entries v_i . v_j (i < j) of the reflectors: v_j is 1 at row
+  // j0 + j, x below it, 0 above; 120 pairs in batches of 32
+  constexpr int kPairs = kQrNb * (kQrNb - 1) / 2;
+#pragma unroll
+  for (int b0 = 0; b0 < kPairs; b0 += 32) {
+    double g[32];
+#pragma unroll
+    for (int p = 0; p < 32; ++p) {
+      g[p] = 0.0;
+      const int pp = b0 + p;
+      if (pp < kPairs) {
+        // pair index pp -> (i, j), i < j, enumerated column by column
+        int j = 1, base = 0;
+#pragma unroll
+        for (int jj = 1; jj < kQrNb; ++jj)
+          if (pp >= jj * (jj - 1) / 2) {
+            j = jj;
+            base = jj * (jj - 1) / 2;
+          }
+        const int i = pp - base;
+#pragma unroll
+        for (int q = 0; q < kQrRows; ++q) {
+          const int row = threadIdx.x + kQrThreads * q;
+          const int gi = j0 + i, gjr = j0 + j;
+          double vi = 0.0, vj = 0.0;
+#pragma unroll
+          for (int c = 0; c < kQrNb; ++c) {
+            if (c == i) vi = row == gi ? 1.0 : (row > gi ? x[q][c] : 0.0);
+            if (c == j) vj = row == gjr ? 1.0 : (row > gjr ? x[q][c] : 0.0);
+          }
+          if (row < m && j < nb) g[p] += vi * vj;
+        }
+      }
+    }
+    double r[32];
+#pragma unroll
+    for (int p = 0; p < 32; ++p) r[p] = g[p];
+    const double v = qr_reduce_scatter<32>(r);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < 32) red[buf][wave * 32 + lane] = v;
+    __syncthreads();
+    if (threadIdx.x < 32 && b0 + (int)threadIdx.x < kPairs) {
+      double t = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < kQrWaves; ++wv) t += red[buf][wv * 32 + threadIdx.x];
+      gram[b0 + threadIdx.x] = t;   // packed pair order
+    }
+    buf ^= 1;
+  }
+  __syncthreads();
+  // lane i builds row i of T: T[i][j] needs only T[i][i..j-1] (its own row)
+  if (threadIdx.x < kQrNb) {
+    const int i = threadIdx.x;
+    double row[kQrNb];
+#pragma unroll
+    for (int j = 0; j < kQrNb; ++j) {
+      const double tj = j < nb ? tau[j0 + j] : 0.0;
+      double v = 0.0;
+      if (i < j) {
+#pragma unroll
+        for (int l = 0; l < j; ++l)
+          if (l >= i) v += row[l] * gram[j * (j - 1) / 2 + l];
+        v *= -tj;
+      } else if (i == j) {
+        v = tj;
+      }
+      row[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < kQrNb; ++j) tl[i * kQrNb + j] = row[j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kQrNb * kQrNb; e += kQrThreads) tf[(j0 / kQrNb) * kQrNb * kQrNb + e] = tl[e];
+}
+
+// reflector j of the panel at this thread's rows: 1 at row j0+j, X below, 0 above
+__device__ inline void qr_load_v(const double* __restrict__ xc, int m, int j0, int nb, int j, double (&v)[kQrRows]) {
+  const int gj = j0 + j;
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int row = threadIdx.x + kQrThreads * q;
+    v[q] = j >= nb ? 0.0 : (row == gj ? 1.0 : ((row > gj && row < m) ? xc[(int64_t)gj * m + row] : 0.0));
+  }
+}
+
+// apply the panel j0 .. j0+nb-1 (reflectors in X, triangular factor T) to
+// columns c0 .. c0+ncols-1 of Y: Y -= V T^T (V^T Y) in the factorisation
+// (transpose = 1: H_{nb-1} ... H_0 Y), Y -= V T (V^T Y) for the accumulation
+// of Q (transpose = 0: H_0 ... H_{nb-1} Y)
+__global__ void __launch_bounds__(kQrThreads) qr_apply_kernel(const double* __restrict__ xc,
+                                                              const double* __restrict__ tf, double* y, int m, int j0,
+                                                              int nb, int c0, int ncols, int transpose) {
+  constexpr int NW = kQrNb * kQrCb;   // 64 entries of W = V^T Y
+  __shared__ double red[kQrWaves * NW];
+  __shared__ double sw[NW], sw2[NW], st[kQrNb * kQrNb];
+  for (int e = threadIdx.x; e < kQrNb * kQrNb; e += kQrThreads) st[e] = tf[(j0 / kQrNb) * kQrNb * kQrNb + e];
+  const int cb0 = c0 + blockIdx.x * kQrCb;
+  double yv[kQrRows][kQrCb];
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int row = threadIdx.x + kQrThreads * q;
+#pragma unroll
+    for (int c = 0; c < kQrCb; ++c)
+      yv[q][c] = (row < m && cb0 + c < c0 + ncols) ? y[(int64_t)(cb0 + c) * m + row] : 0.0;
+  }
+  double w[NW];
+#pragma unroll
+  for (int j = 0; j < kQrNb; ++j) {
+    double v[kQrRows];
+    qr_load_v(xc, m, j0, nb, j, v);
+#pragma unroll
+    for (int c = 0; c < kQrCb; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) s += v[q] * yv[q][c];
+      w[j * kQrCb + c] = s;
+    }
+  }
+  const double r = qr_reduce_scatter<NW>(w);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  red[wave * NW + lane] = r;
+  __syncthreads();
+  if (threadIdx.x < NW) {
+    double t = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kQrWaves; ++wv) t += red[wv * NW + threadIdx.x];
+    sw[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < NW) {
+    const int j = threadIdx.x / kQrCb, c = threadIdx.x % kQrCb;
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < kQrNb; ++l) t += (transpose ? st[l * kQrNb + j] : st[j * kQrNb + l]) * sw[l * kQrCb + c];
+    sw2[threadIdx.x] = t;
+  }
+  __syncthreads();
+#pragma unroll 2
+  for (int j = 0; j < kQrNb; ++j) {
+    double v[kQrRows];
+    qr_load_v(xc, m, j0, nb, j, v);
+#pragma unroll
+    for (int c = 0; c < kQrCb; ++c) {
+      const double w2 = sw2[j * kQrCb + c];
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) yv[q][c] -= v[q] * w2;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int row = threadIdx.x + kQrThreads * q;
+    if (row < m) {
+#pragma unroll
+      for (int c = 0; c < kQrCb; ++c)
+        if (cb0 + c < c0 + ncols) y[(int64_t)(cb0 + c) * m + row] = yv[q][c];
+    }
+  }
+}
+
 __global__ void eye_kernel(double* qc, int m, int n) {
   const int64_t total = (int64_t)m * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -141,7 +456,7 @@ static unsigned blocks_for(int64_t n) {
 }
 
 struct QrLayout {
-  size_t x, q, r, tau, total;
+  size_t x, q, r, tau, tf, total;
 };
 
 static int32_t qr_check(int32_t n, const tn_tensor* sites, QrLayout& L) {
@@ -168,7 +483,8 @@ static int32_t qr_check(int32_t n, const tn_tensor* sites, QrLayout& L) {
   L.q = al256(mx * 8);
   L.r = L.q + al256(mx * 8);
   L.tau = L.r + al256(std::max<int64_t>(mr, 1) * 8);
-  L.total = L.tau + al256(4096 * 8);
+  L.tf = L.tau + al256(4096 * 8);
+  L.total = L.tf + al256((4096 / kQrNb) * kQrNb * kQrNb * 8);
   int64_t maxn = 1;
   for (int k = 0; k < n; ++k) maxn = std::max(maxn, sites[k].shape[2]);
   if (maxn > 4096) return fail(TN_ERR_UNSUPPORTED, "bond dimension above 4096");
@@ -201,6 +517,7 @@ int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* logn
   double* qc = reinterpret_cast<double*>(ws + L.q);
   double* r = reinterpret_cast<double*>(ws + L.r);
   double* tau = reinterpret_cast<double*>(ws + L.tau);
+  double* tf = reinterpret_cast<double*>(ws + L.tf);
   hipLaunchKernelGGL(one_kernel, dim3(1), dim3(64), 0, st, r);
   for (int k = 0; k < n_sites; ++k) {
     const int dk = (int)sites[k].shape[0], d = (int)sites[k].shape[1], dn = (int)sites[k].shape[2];
@@ -208,13 +525,30 @@ int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* logn
     double* a = static_cast<double*>(sites[k].data);
     dim3 g((unsigned)((d * dn + 63) / 64), (unsigned)((dk + 63) / 64));
     hipLaunchKernelGGL(absorb_kernel, g, dim3(256), 0, st, r, a, xc, dk, d, dn);
-    for (int j = 0; j < n; ++j) {
-      hipLaunchKernelGGL(reflector_kernel, dim3(1), dim3(256), 0, st, xc, tau, m, j);
-      if (j + 1 < n) hipLaunchKernelGGL(reflect_cols_kernel, dim3(n - j - 1), dim3(256), 0, st, xc, tau, xc, m, j, j + 1);
+    if (m <= kQrThreads * kQrRows) {
+      for (int j0 = 0; j0 < n; j0 += kQrNb) {
+        const int nb = std::min(kQrNb, n - j0);
+        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(kQrThreads), 0, st, xc, tau, tf, m, j0, nb);
+        const int rest = n - j0 - nb;
+        if (rest > 0)
+          hipLaunchKernelGGL(qr_apply_kernel, dim3((unsigned)((rest + kQrCb - 1) / kQrCb)), dim3(kQrThreads), 0, st, xc,
+                             tf, xc, m, j0, nb, j0 + nb, rest, 1);
+      }
+      hipLaunchKernelGGL(eye_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, st, qc, m, n);
+      for (int j0 = (n - 1) / kQrNb * kQrNb; j0 >= 0; j0 -= kQrNb) {
+        const int nb = std::min(kQrNb, n - j0);
+        hipLaunchKernelGGL(qr_apply_kernel, dim3((unsigned)((n - j0 + kQrCb - 1) / kQrCb)), dim3(kQrThreads), 0, st, xc,
+                           tf, qc, m, j0, nb, j0, n - j0, 0);
+      }
+    } else {
+      for (int j = 0; j < n; ++j) {
+        hipLaunchKernelGGL(reflector_kernel, dim3(1), dim3(256), 0, st, xc, tau, m, j);
+        if (j + 1 < n) hipLaunchKernelGGL(reflect_cols_kernel, dim3(n - j - 1), dim3(256), 0, st, xc, tau, xc, m, j, j + 1);
+      }
+      hipLaunchKernelGGL(eye_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, st, qc, m, n);
+      for (int j = n - 1; j >= 0; --j)
+        hipLaunchKernelGGL(reflect_cols_kernel, dim3(n - j), dim3(256), 0, st, xc, tau, qc, m, j, j);
     }
-    hipLaunchKernelGGL(eye_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, st, qc, m, n);
-    for (int j = n - 1; j >= 0; --j)
-      hipLaunchKernelGGL(reflect_cols_kernel, dim3(n - j), dim3(256), 0, st, xc, tau, qc, m, j, j);
     hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, st, xc, qc, a, r, m, n);
     TN_TRY(hip_check(hipGetLastError(), "canonicalize"));
   }

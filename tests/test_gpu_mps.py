@@ -233,6 +233,24 @@ def test_left_canonicalize_matches_oracle():
         np.testing.assert_allclose(q.T @ q, np.eye(dn), atol=1e-12)
 
 
+def test_left_canonicalize_blocked_and_column_paths():
+    """Bonds that are not multiples of the 16-column panel, and two sites of
+    more than 2048 rows (the column-by-column path), against the oracle."""
+    dims = [1, 2, 4, 8, 13, 26, 50, 99, 190, 380, 700, 1100, 1200, 600, 300, 150, 75, 37, 18, 9, 4, 2, 1]
+    raw = inputs.random_mps(len(dims) - 1, 2, 1024, 207, dims=dims)
+    ref, lognorm_ref = oracle.left_canonicalize(raw)
+    sites = [torch.tensor(x, dtype=torch.float64, device=DEV) for x in raw]
+    ln = tn.mps_left_canonicalize(sites)
+    torch.cuda.synchronize()
+    assert abs(float(ln.cpu()) - lognorm_ref) < 1e-10 * max(1, abs(lognorm_ref))
+    for k, (a, b) in enumerate(zip(sites, ref)):
+        got = a.cpu().numpy()
+        np.testing.assert_allclose(got, b, atol=1e-9, err_msg=f"site {k}")
+        dk, d, dn = b.shape
+        q = got.reshape(dk * d, dn)
+        np.testing.assert_allclose(q.T @ q, np.eye(dn), atol=1e-11, err_msg=f"site {k}")
+
+
 # ---------------------------------------------------------------------------
 # full-size operator sweep (chi = 1024, N = 64, XXZ bond 5) through exact properties
 
