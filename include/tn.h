@@ -137,6 +137,22 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
                             tn_tensor* out, void* workspace, size_t ws_bytes, int32_t prec,
                             void* stream);
 
+/* Contraction order for the same network description (host only: reads
+ * shapes, never data).  method TN_ORDER_GREEDY: repeatedly contract the
+ * connected pair of nodes with the fewest flops; TN_ORDER_OPTIMAL: the
+ * exact minimum total flops over all pairwise contraction trees (dynamic
+ * programming over node subsets, at most 12 nodes per connected component,
+ * else TN_ERR_UNSUPPORTED).  Cost of a pairwise step: 2 x the product of the
+ * extents of all labels on the two nodes.  Trace labels come first.
+ * order (caller-owned, capacity >= number of connected labels) receives a
+ * label order for tn_contract_network, *n_order its length, *flops the
+ * total pairwise flops (traces excluded). */
+#define TN_ORDER_GREEDY 0
+#define TN_ORDER_OPTIMAL 1
+int32_t tn_network_order(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels,
+                         const int32_t* offsets, int32_t method, int32_t* order, int32_t* n_order,
+                         double* flops);
+
 /* ---------------------------------------------------------------------
  * MPS inner product <psi|phi> (the chain network of Fig. 3a, contracted
  * site by site from the left).  psi[k], phi[k] are TN_F32 [D_k, d, D_{k+1}]

@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     mps_inner,
     mps_inner_batched,
     mps_left_canonicalize,
+    network_order,
     outer_product,
     softmax_xent,
     tensordot,
@@ -25,5 +26,7 @@ from .api import (  # noqa: F401
     tune_num_configs,
     tune_set_level,
 )
+
+from ._lib import TNError  # noqa: F401
 
 __version__ = "0.1.0"

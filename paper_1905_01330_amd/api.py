@@ -72,10 +72,36 @@ def outer_product(a, b, out=None):
     return out
 
 
+def network_order(tensors, labels, method="greedy"):
+    """A contraction order for contract_network and its pairwise flop count.
+
+    method "greedy" (cheapest connected pair first) or "optimal" (exact
+    minimum over contraction trees, up to 12 nodes per connected part).
+    Reads only the shapes."""
+    flat, offs = [], [0]
+    for l in labels:
+        flat.extend(int(x) for x in l)
+        offs.append(len(flat))
+    nodes = L.tensor_array(tensors)
+    n_conn = sum(1 for x in flat if x >= 0) // 2 + 1
+    order = (C.c_int32 * max(n_conn, 1))()
+    n_order = C.c_int32(0)
+    flops = C.c_double(0.0)
+    code = {"greedy": 0, "optimal": 1}[method]
+    L.check(L.lib().tn_network_order(len(tensors), nodes, L.int_array(flat), L.int_array(offs), code, order,
+                                     C.byref(n_order), C.byref(flops)))
+    return [int(order[i]) for i in range(n_order.value)], float(flops.value)
+
+
 def contract_network(tensors, labels, order=None, out=None, prec="fp32"):
-    """ncon (Appendix B): labels >= 0 connect, labels < 0 are outputs -1, -2, ..."""
+    """ncon (Appendix B): labels >= 0 connect, labels < 0 are outputs -1, -2, ...
+
+    order: a list of connected labels, None (ascending labels), or "greedy" /
+    "optimal" (network_order)."""
     for t in tensors:
         _dev(t)
+    if isinstance(order, str):
+        order = network_order(tensors, labels, order)[0]
     flat, offs = [], [0]
     for l in labels:
         flat.extend(int(x) for x in l)

@@ -479,3 +479,20 @@ def test_tiny_contracted_and_free_extents(prec):
     res = torch.empty((16, 3000), device=DEV)
     tn.contract_between(big[:, ::2], gpu(b), [1], [0], out=res.t(), prec=prec)
     check(host(res).T, a.astype(np.float64) @ b, np.abs(a).astype(np.float64) @ np.abs(b), tol, "strided, permuted out")
+
+
+@pytest.mark.parametrize("method", ["greedy", "optimal"])
+def test_network_with_searched_order(method):
+    """A six-node network with a trace, a double edge and open legs,
+    contracted in the searched order: equal to the oracle's (any order gives
+    the same tensor up to rounding)."""
+    rng = np.random.default_rng(25)
+    labels = [[0, 1, 7, 7], [1, 2, -1], [2, 3, 4], [3, 4, 5, -2], [5, 6], [6, 0, -3]]
+    dims = {0: 6, 1: 7, 2: 5, 3: 4, 4: 3, 5: 8, 6: 9, 7: 2, -1: 3, -2: 5, -3: 4}
+    ts = [f32(rng.standard_normal([dims[l] for l in ls]) / 3) for ls in labels]
+    ref = oracle.contract_network([t.astype(np.float64) for t in ts], labels)
+    order, flops = tn.network_order([gpu(t) for t in ts], labels, method)
+    assert flops > 0 and order[0] == 7
+    out = tn.contract_network([gpu(t) for t in ts], labels, order=method)
+    scale = oracle.contract_network([np.abs(t).astype(np.float64) for t in ts], labels)
+    check(host(out), ref, scale, 1e-5, f"network {method}")
