@@ -58,6 +58,7 @@ struct Launch {
   size_t tile_off;   // index into the tile-start table
   int32_t tiles;
   int cfg;
+  int variant;   // gather variant shared by every problem of the launch
 };
 
 struct BatchPlan {
@@ -192,12 +193,19 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
       for (int bi = 0; bi < 3; ++bi) {
         auto& v = bins[bi];
         if (v.empty()) continue;
+        // one launch per tile size (splitting a step into more launches only
+        // serialises it): the fast gathers when every problem allows the
+        // same variant, else the run-time gathers
+        int var = grouped_variant(v[0].second);
+        for (auto& e : v)
+          if (grouped_variant(e.second) != var) var = 0;
         std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
         Launch L;
         L.prob_off = P.probs.size();
         L.n_probs = (int32_t)v.size();
         L.tile_off = P.tstart.size();
         L.cfg = bi;
+        L.variant = var;
         const int tm = grouped_tile_m(bi), tn_ = grouped_tile_n(bi);
         int64_t t = 0;
         for (auto& e : v) {
@@ -275,7 +283,8 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   hipLaunchKernelGGL(batched_init_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains);
   TN_TRY(hip_check(hipGetLastError(), "batched init"));
   for (const Launch& L : Q.launches)
-    TN_TRY(launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off, L.n_probs, L.tiles, prec, L.cfg, st));
+    TN_TRY(launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off, L.n_probs, L.tiles, prec, L.cfg, L.variant,
+                               st));
   hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains, out2);
   return hip_check(hipGetLastError(), "batched finish");
 }

@@ -45,7 +45,7 @@ static const int kGroupedCfg[3] = {3, 6, 7};
 int grouped_tile_m(int cfg) { return kCfgs[kGroupedCfg[cfg]].bm; }
 int grouped_tile_n(int cfg) { return kCfgs[kGroupedCfg[cfg]].bn; }
 
-static GroupedFn pick_grouped(int prec, int cfg) { return grouped_fn_prec(prec, cfg); }
+static GroupedFn pick_grouped(int prec, int cfg, int variant) { return grouped_fn_prec(prec, cfg, variant); }
 
 static int g_forced_cfg = -1;
 
@@ -155,11 +155,24 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
   return launch_gemm_cfg(d, prec, cfg, st);
 }
 
+// the gather modes the grouped kernel derives for problem p (the same rules)
+int grouped_variant(const Gemm2D& p) {
+  auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  const int am = (p.sak == 1 && p.K % 4 == 0 && p.sam % 4 == 0 && al(p.a)) ? LOAD_KVEC
+               : (p.sam == 1 && p.M % 4 == 0 && p.sak % 4 == 0 && al(p.a)) ? LOAD_MNVEC
+                                                                            : LOAD_GENERIC;
+  const int bm = (p.sbk == 1 && p.K % 4 == 0 && p.sbn % 4 == 0 && al(p.b)) ? LOAD_KVEC
+               : (p.sbn == 1 && p.N % 4 == 0 && p.sbk % 4 == 0 && al(p.b)) ? LOAD_MNVEC
+                                                                            : LOAD_GENERIC;
+  if (am == LOAD_GENERIC || bm == LOAD_GENERIC) return 0;
+  return 1 + (am == LOAD_MNVEC ? 2 : 0) + (bm == LOAD_MNVEC ? 1 : 0);
+}
+
 int32_t launch_gemm_grouped(const Gemm2D* dev_probs, const int32_t* dev_tile_start, int32_t n_probs,
-                            int32_t total_tiles, int32_t prec, int cfg, hipStream_t st) {
+                            int32_t total_tiles, int32_t prec, int cfg, int variant, hipStream_t st) {
   if (n_probs <= 0 || total_tiles <= 0) return TN_OK;
   const Cfg& g = kCfgs[kGroupedCfg[cfg]];
-  hipLaunchKernelGGL(pick_grouped(prec, cfg), dim3((unsigned)total_tiles), dim3(g.wm * g.wn * 64), 0, st, dev_probs,
+  hipLaunchKernelGGL(pick_grouped(prec, cfg, variant), dim3((unsigned)total_tiles), dim3(g.wm * g.wn * 64), 0, st, dev_probs,
                      dev_tile_start, n_probs);
   return hip_check(hipGetLastError(), "grouped gemm launch");
 }

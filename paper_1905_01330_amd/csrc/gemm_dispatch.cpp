@@ -6,10 +6,10 @@ GemmFn gemm_fn_fp32(int cfg, int variant);
 GemmFn gemm_fn_bf16(int cfg, int variant);
 GemmFn gemm_fn_x6(int cfg, int variant);
 GemmFn gemm_fn_x3(int cfg, int variant);
-GroupedFn grouped_fn_fp32(int cfg);
-GroupedFn grouped_fn_bf16(int cfg);
-GroupedFn grouped_fn_x6(int cfg);
-GroupedFn grouped_fn_x3(int cfg);
+GroupedFn grouped_fn_fp32(int cfg, int variant);
+GroupedFn grouped_fn_bf16(int cfg, int variant);
+GroupedFn grouped_fn_x6(int cfg, int variant);
+GroupedFn grouped_fn_x3(int cfg, int variant);
 
 GemmFn gemm_fn_prec(int prec, int cfg, int variant) {
   switch (prec) {
@@ -20,12 +20,12 @@ GemmFn gemm_fn_prec(int prec, int cfg, int variant) {
   }
 }
 
-GroupedFn grouped_fn_prec(int prec, int cfg) {
+GroupedFn grouped_fn_prec(int prec, int cfg, int variant) {
   switch (prec) {
-    case TN_PREC_FP32: return grouped_fn_fp32(cfg);
-    case TN_PREC_BF16: return grouped_fn_bf16(cfg);
-    case TN_PREC_SPLIT_BF16: return grouped_fn_x6(cfg);
-    default: return grouped_fn_x3(cfg);
+    case TN_PREC_FP32: return grouped_fn_fp32(cfg, variant);
+    case TN_PREC_BF16: return grouped_fn_bf16(cfg, variant);
+    case TN_PREC_SPLIT_BF16: return grouped_fn_x6(cfg, variant);
+    default: return grouped_fn_x3(cfg, variant);
   }
 }
 }  // namespace tn

@@ -3,5 +3,5 @@
 
 namespace tn {
 GemmFn gemm_fn_fp32(int cfg, int variant) { return gemm_fn<P_FP32>(cfg, variant); }
-GroupedFn grouped_fn_fp32(int cfg) { return grouped_fn<P_FP32>(cfg); }
+GroupedFn grouped_fn_fp32(int cfg, int variant) { return grouped_fn<P_FP32>(cfg, variant); }
 }  // namespace tn

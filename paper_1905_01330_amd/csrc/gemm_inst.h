@@ -38,10 +38,12 @@ __global__ void __launch_bounds__(WM* WN * WK * 64)
 // Grouped launch: the workgroup finds its problem by binary search over the
 // per-problem first-tile table, then expands the compact 2-D description
 // into a full descriptor held in LDS.
-template <int P, int BM, int BN, int BK, int WM, int WN>
+// AMODE / BMODE as for gemm_kernel: the fast gathers when the host has
+// checked that every problem of the launch has those layouts, else -1.
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE = -1, int BMODE = -1>
 __global__ void __launch_bounds__(WM* WN * 64)
     gemm_grouped_kernel(const Gemm2D* probs, const int32_t* tile_start, int32_t n_probs) {
-  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, -1, -1>::lds_bytes];
+  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::lds_bytes];
   __shared__ GemmDesc sd;
   __shared__ int32_t s_prob;
   const int bid = blockIdx.x;
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
     d.c_mode = (p.scm == 1 && p.M % 4 == 0 && p.scn % 4 == 0 && al(p.c)) ? STORE_MVEC : STORE_SCALAR;
   }
   __syncthreads();
-  GemmTile<P, BM, BN, BK, WM, WN, -1, -1>::run(sd, sd.gk, bid - tile_start[s_prob], 0, smem);
+  GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::run(sd, sd.gk, bid - tile_start[s_prob], 0, smem);
 }
 
 
@@ -129,15 +131,25 @@ GemmFn gemm_fn(int cfg, int variant) {
   }
 }
 
-template <int P>
-GroupedFn grouped_fn(int cfg) {
+template <int P, int AM, int BM_>
+GroupedFn grouped_fn_modes(int cfg) {
   switch (cfg) {
-    case 0: return gemm_grouped_kernel<P, 128, 128, 32, 2, 2>;
-    case 1: return gemm_grouped_kernel<P, 64, 64, 32, 2, 2>;
-    default: return gemm_grouped_kernel<P, 32, 32, 32, 1, 1>;
+    case 0: return gemm_grouped_kernel<P, 128, 128, 32, 2, 2, AM, BM_>;
+    case 1: return gemm_grouped_kernel<P, 64, 64, 32, 2, 2, AM, BM_>;
+    default: return gemm_grouped_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }
 
-
+// variant as for gemm_fn: 0 run-time gathers; 1..4 (A, B) = (K,K) (K,MN) (MN,K) (MN,MN)
+template <int P>
+GroupedFn grouped_fn(int cfg, int variant) {
+  switch (variant) {
+    case 1: return grouped_fn_modes<P, LOAD_KVEC, LOAD_KVEC>(cfg);
+    case 2: return grouped_fn_modes<P, LOAD_KVEC, LOAD_MNVEC>(cfg);
+    case 3: return grouped_fn_modes<P, LOAD_MNVEC, LOAD_KVEC>(cfg);
+    case 4: return grouped_fn_modes<P, LOAD_MNVEC, LOAD_MNVEC>(cfg);
+    default: return grouped_fn_modes<P, -1, -1>(cfg);
+  }
+}
 
 }  // namespace tn

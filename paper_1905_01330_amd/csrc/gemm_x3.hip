@@ -3,5 +3,5 @@
 
 namespace tn {
 GemmFn gemm_fn_x3(int cfg, int variant) { return gemm_fn<P_X3>(cfg, variant); }
-GroupedFn grouped_fn_x3(int cfg) { return grouped_fn<P_X3>(cfg); }
+GroupedFn grouped_fn_x3(int cfg, int variant) { return grouped_fn<P_X3>(cfg, variant); }
 }  // namespace tn

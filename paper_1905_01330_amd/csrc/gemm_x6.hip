@@ -3,5 +3,5 @@
 
 namespace tn {
 GemmFn gemm_fn_x6(int cfg, int variant) { return gemm_fn<P_X6>(cfg, variant); }
-GroupedFn grouped_fn_x6(int cfg) { return grouped_fn<P_X6>(cfg); }
+GroupedFn grouped_fn_x6(int cfg, int variant) { return grouped_fn<P_X6>(cfg, variant); }
 }  // namespace tn

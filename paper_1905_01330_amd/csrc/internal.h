@@ -60,8 +60,11 @@ struct Gemm2D {
   const uint32_t* a_scale_bits;
   uint32_t* c_absmax;
 };
+// variant: 0 run-time gathers; 1..4 fast gathers, for launches whose every
+// problem passes grouped_variant with that value
+int grouped_variant(const Gemm2D& p);
 int32_t launch_gemm_grouped(const Gemm2D* dev_probs, const int32_t* dev_tile_start, int32_t n_probs,
-                            int32_t total_tiles, int32_t prec, int cfg, hipStream_t st);
+                            int32_t total_tiles, int32_t prec, int cfg, int variant, hipStream_t st);
 int grouped_tile_m(int cfg);
 int grouped_tile_n(int cfg);
 

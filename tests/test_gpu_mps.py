@@ -114,6 +114,25 @@ def test_inner_batched_uneven(prec):
     assert value_rel(m, s, got[5, 0], got[5, 1]) <= 4 * TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_inner_batched_aligned_bonds(prec):
+    """Bond dimensions that are multiples of four: the grouped launches take
+    the fast gathers."""
+    rng = np.random.default_rng(31)
+    chains, refs = [], []
+    for i in range(12):
+        n, chi = int(rng.integers(6, 30)), int(rng.choice([8, 16, 32, 64, 128]))
+        psi, phi = inputs.uneven_chain(i, n, chi, seed=409)
+        psi, phi = r32(psi), r32(phi)
+        refs.append(oracle.mps_inner(psi, phi))
+        chains.append((g32(psi), g32(phi)))
+    out = tn.mps_inner_batched(chains, prec=prec)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i, (mr, sr) in enumerate(refs):
+        assert value_rel(got[i, 0], got[i, 1], mr, sr) <= 4 * TOL[prec], i
+
+
 def test_inner_batched_sample_of_full_workload():
     """Eight chains drawn from the 512-chain uneven workload (N up to 256, chi up to 512)."""
     shapes = inputs.uneven_chain_shapes()
