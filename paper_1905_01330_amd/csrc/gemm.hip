@@ -34,7 +34,9 @@ int gemm_num_cfgs() { return kNumCfgs; }
 
 // fast gathers need one merged K axis and vector-friendly layouts on both operands
 static int gemm_variant(const GemmDesc& d) {
-  if (d.gk.n != 1 || d.a_mode == LOAD_GENERIC || d.b_mode == LOAD_GENERIC) return 0;
+  if (d.gk.n != 1 || d.a_mode == LOAD_GENERIC || d.b_mode == LOAD_GENERIC || d.a_mode == LOAD_MNSCALAR ||
+      d.b_mode == LOAD_MNSCALAR)
+    return 0;
   return 1 + (d.a_mode == LOAD_MNVEC ? 2 : 0) + (d.b_mode == LOAD_MNVEC ? 1 : 0);
 }
 

@@ -173,6 +173,8 @@ struct OperandLoader {
   int mode;
   const float* base;
   int K;
+  int nrows;
+  int row0;
   float scale;
 
   // offset of contracted index k: one multiply for a single merged axis, else
@@ -190,15 +192,17 @@ struct OperandLoader {
     return o;
   }
 
-  __device__ __forceinline__ void init(int mode_, const float* base_, const Group& grows, int row0, int nrows, int K_,
+  __device__ __forceinline__ void init(int mode_, const float* base_, const Group& grows, int row0_, int nrows_, int K_,
                               float scale_) {
     mode = mode_;
     base = base_;
     K = K_;
+    nrows = nrows_;
+    row0 = row0_;
     scale = scale_;
     rowok = 0;
     const int tid = threadIdx.x;
-    if (mode != LOAD_MNVEC) {
+    if (mode != LOAD_MNVEC && mode != LOAD_MNSCALAR) {
 #pragma unroll
       for (int v = 0; v < VK; ++v) {
         int idx = tid + v * NT;
@@ -264,7 +268,24 @@ struct OperandLoader {
         const int64_t ks = gk.s[KIDX][last];
         const bool ok = (rowok >> v) & 1u;
         f32x4_t x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0, x2 = x0, x3 = x0;
-        if (run) {
+        if (mode == LOAD_MNSCALAR) {
+          // rows r .. r+3 are consecutive addresses; rows past the end read 0
+          const int r = row0 + (idx / KQ) * 4;
+          auto col = [&](int kk) {
+            f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+            if (ok && kk < K) {
+              const float* p = base + rowoff[v] + koff(gk, kk);
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (r + i < nrows) x[i] = p[i];
+            }
+            return x;
+          };
+          x0 = col(k + 0);
+          x1 = col(k + 1);
+          x2 = col(k + 2);
+          x3 = col(k + 3);
+        } else if (run) {
           const float* p = base + rowoff[v] + ko;
           if (ok && k + 0 < K) x0 = *reinterpret_cast<const f32x4_t*>(p);
           if (ok && k + 1 < K) x1 = *reinterpret_cast<const f32x4_t*>(p + ks);
@@ -286,7 +307,7 @@ struct OperandLoader {
 
   __device__ __forceinline__ void store(char* lds) {
     const int tid = threadIdx.x;
-    if (mode != LOAD_MNVEC) {
+    if (mode != LOAD_MNVEC && mode != LOAD_MNSCALAR) {
 #pragma unroll
       for (int v = 0; v < VK; ++v) {
         int idx = tid + v * NT;

@@ -184,12 +184,21 @@ static bool vec4_ok(const Group& inner, int ti, const Group& other, int oi, cons
   return true;
 }
 
+// rows unit-stride, in runs of four that never straddle an outer index
+static bool mn_scalar_ok(const Group& rows, int ti) {
+  if (rows.n < 1) return false;
+  const int last = rows.n - 1;
+  return rows.s[ti][last] == 1 && (rows.n == 1 || rows.dim[last] % 4 == 0);
+}
+
 void choose_modes(GemmDesc& d) {
   d.a_mode = vec4_ok(d.gk, 0, d.gm, 0, d.a, d.a_bs) ? LOAD_KVEC
            : vec4_ok(d.gm, 0, d.gk, 0, d.a, d.a_bs) ? LOAD_MNVEC
+           : mn_scalar_ok(d.gm, 0)                   ? LOAD_MNSCALAR
                                                      : LOAD_GENERIC;
   d.b_mode = vec4_ok(d.gk, 1, d.gn, 0, d.b, d.b_bs) ? LOAD_KVEC
            : vec4_ok(d.gn, 0, d.gk, 1, d.b, d.b_bs) ? LOAD_MNVEC
+           : mn_scalar_ok(d.gn, 0)                   ? LOAD_MNSCALAR
                                                      : LOAD_GENERIC;
   d.c_mode = vec4_ok(d.gm, 1, d.gn, 1, d.c, d.c_bs) ? STORE_MVEC : STORE_SCALAR;
 }

@@ -496,3 +496,21 @@ def test_network_with_searched_order(method):
     out = tn.contract_network([gpu(t) for t in ts], labels, order=method)
     scale = oracle.contract_network([np.abs(t).astype(np.float64) for t in ts], labels)
     check(host(out), ref, scale, 1e-5, f"network {method}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "bf16"])
+def test_row_contiguous_operands_of_odd_extent(prec):
+    """Operands whose free index is unit-stride but of odd extent or not
+    16-byte aligned: the row-contiguous gathers with scalar loads."""
+    rng = np.random.default_rng(26)
+    M, K, N = 261, 133, 197
+    a = f32(rng.standard_normal((M, K)))
+    b = f32(rng.standard_normal((K, N)))
+    ga = gpu(a.T.copy()).t()                       # M unit-stride, M odd
+    buf = gpu(np.zeros(K * N + 1, dtype=np.float32))
+    gb = buf[1:].view(K, N)                        # N unit-stride, misaligned rows
+    gb.copy_(gpu(b))
+    ref = a.astype(np.float64) @ b.astype(np.float64)
+    scale = np.abs(a).astype(np.float64) @ np.abs(b).astype(np.float64)
+    out = tn.contract_between(ga, gb, [1], [0], prec=prec)
+    check(host(out), ref, scale, TOL[prec], "odd row-contiguous")
