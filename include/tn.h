@@ -279,6 +279,14 @@ int32_t tn_tune_last_choice(void);
  * Meant for measurement. */
 int32_t tn_tune_force_config(int32_t cfg);
 int32_t tn_tune_num_configs(void);
+/* Pin the tile of every site step of the uneven batched inner product:
+ * 0: 128 x 128, 1: 64 x 64, 2: 32 x 32, 3: 64 x 64 in two k-slices; -1
+ * restores the per-step choice.  The tile tables are written by
+ * tn_mps_inner_batched_upload, so the setting must not change between an
+ * upload and the launches that use it (a launch with another setting stays
+ * in bounds but computes wrong values).  Meant for measurement and tests.
+ * TN_ERR_INVALID_ARGUMENT outside -1 .. 3. */
+int32_t tn_tune_force_grouped_config(int32_t cfg);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     tensordot,
     trace_edge,
     tune_force_config,
+    tune_force_grouped_config,
     tune_last_choice,
     tune_num_configs,
     tune_set_level,

@@ -75,6 +75,7 @@ _PROTOS = {
     "tn_tune_set_level": (I32, [I32]),
     "tn_tune_last_choice": (I32, []),
     "tn_tune_force_config": (I32, [I32]),
+    "tn_tune_force_grouped_config": (I32, [I32]),
     "tn_tune_num_configs": (I32, []),
 }
 

@@ -262,6 +262,11 @@ def tune_force_config(cfg: int):
     L.check(L.lib().tn_tune_force_config(int(cfg)))
 
 
+def tune_force_grouped_config(cfg: int):
+    """Pin the tile of the uneven batched inner product's site steps (-1: per-step choice)."""
+    L.check(L.lib().tn_tune_force_grouped_config(int(cfg)))
+
+
 def tune_last_choice() -> int:
     return int(L.lib().tn_tune_last_choice())
 

@@ -78,10 +78,41 @@ bool is_contiguous(const tn_tensor& t) {
   return true;
 }
 
-int bin_of(int64_t M, int64_t N) {
-  if (M <= 32 && N <= 32) return 2;
-  if (M * N >= 4ll * 128 * 128) return 0;
-  return 1;
+// Tile size for one site step, shared by all of its problems (one launch per
+// step and product).  A step is usually too small to fill the chip with
+// 128 x 128 tiles, so its time is the latency of one tile rather than the
+// total work: the estimate is, in units of one wave's 32 x 32 block times one
+// k, the larger of the longest wave's work and the total padded work spread
+// over the 1024 SIMDs, divided by a per-wave efficiency of the tile shape.
+//   0: 128 x 128 (four 64 x 64 waves)   1: 64 x 64 (four 32 x 32 waves)
+//   3: 64 x 64 in two k-slices (eight waves, each over half of K)
+//   2: 32 x 32 when every problem of the step fits one such tile
+int step_cfg(const std::vector<Gemm2D>& v) {
+  bool tiny = true;
+  for (const Gemm2D& q : v) tiny = tiny && q.M <= 32 && q.N <= 32;
+  if (tiny) return 2;
+  struct Cand {
+    int cfg, bm;
+    double per_wave;  // blocks x k per wave, per k of the problem
+    double eff;
+  };
+  static const Cand cands[] = {{0, 128, 4.0, 1.0}, {1, 64, 1.0, 0.7}, {3, 64, 0.5, 0.6}};
+  int best = 0;
+  double best_t = 1e300;
+  for (const Cand& c : cands) {
+    double work = 0, lat = 0;
+    for (const Gemm2D& q : v) {
+      const double tiles = (double)((q.M + c.bm - 1) / c.bm) * ((q.N + c.bm - 1) / c.bm);
+      work += tiles * (c.bm / 32) * (c.bm / 32) * q.K;
+      lat = std::max(lat, c.per_wave * q.K);
+    }
+    const double t = std::max(lat, work / 1024.0) / c.eff;
+    if (t < best_t * 0.999) {
+      best_t = t;
+      best = c.cfg;
+    }
+  }
+  return best;
 }
 
 int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const tn_tensor* phi, char* ws,
@@ -147,9 +178,10 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
     o += align256b((size_t)(r.n + 1) * 4);
   }
   P.chain_bytes = o;
+  const int forced = forced_grouped_cfg();
   for (int j = 0; j < max_n; ++j) {
     for (int g = 0; g < 2; ++g) {
-      std::vector<std::pair<int64_t, Gemm2D>> bins[3];
+      std::vector<std::pair<int64_t, Gemm2D>> v;
       for (int c = 0; c < n_chains; ++c) {
         const int n = off[c + 1] - off[c];
         if (j >= n) continue;
@@ -188,35 +220,34 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
           q.scn = 1;
           q.c_absmax = r.slots + j + 1;
         }
-        bins[bin_of(q.M, q.N)].push_back({(int64_t)q.M * q.N * q.K, q});
+        v.push_back({(int64_t)q.M * q.N * q.K, q});
       }
-      for (int bi = 0; bi < 3; ++bi) {
-        auto& v = bins[bi];
-        if (v.empty()) continue;
-        // one launch per tile size (splitting a step into more launches only
-        // serialises it): the fast gathers when every problem allows the
-        // same variant, else the run-time gathers
-        int var = grouped_variant(v[0].second);
-        for (auto& e : v)
-          if (grouped_variant(e.second) != var) var = 0;
-        std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
-        Launch L;
-        L.prob_off = P.probs.size();
-        L.n_probs = (int32_t)v.size();
-        L.tile_off = P.tstart.size();
-        L.cfg = bi;
-        L.variant = var;
-        const int tm = grouped_tile_m(bi), tn_ = grouped_tile_n(bi);
-        int64_t t = 0;
-        for (auto& e : v) {
-          P.tstart.push_back((int32_t)t);
-          t += (int64_t)((e.second.M + tm - 1) / tm) * ((e.second.N + tn_ - 1) / tn_);
-          P.probs.push_back(e.second);
-        }
-        if (t >= (1ll << 31)) return fail(TN_ERR_UNSUPPORTED, "too many tiles in one step");
-        L.tiles = (int32_t)t;
-        P.launches.push_back(L);
+      if (v.empty()) continue;
+      // one launch per step and product (more launches would only serialise
+      // it): the fast gathers when every problem allows the same variant,
+      // else the run-time gathers; the largest problems take the first tiles
+      int var = grouped_variant(v[0].second);
+      for (auto& e : v)
+        if (grouped_variant(e.second) != var) var = 0;
+      std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+      std::vector<Gemm2D> qs;
+      for (auto& e : v) qs.push_back(e.second);
+      Launch L;
+      L.prob_off = P.probs.size();
+      L.n_probs = (int32_t)v.size();
+      L.tile_off = P.tstart.size();
+      L.cfg = forced >= 0 ? forced : step_cfg(qs);
+      L.variant = var;
+      const int tm = grouped_tile_m(L.cfg), tn_ = grouped_tile_n(L.cfg);
+      int64_t t = 0;
+      for (const Gemm2D& q : qs) {
+        P.tstart.push_back((int32_t)t);
+        t += (int64_t)((q.M + tm - 1) / tm) * ((q.N + tn_ - 1) / tn_);
+        P.probs.push_back(q);
       }
+      if (t >= (1ll << 31)) return fail(TN_ERR_UNSUPPORTED, "too many tiles in one step");
+      L.tiles = (int32_t)t;
+      P.launches.push_back(L);
     }
   }
   P.chain_tab = align256b(P.chain_bytes);

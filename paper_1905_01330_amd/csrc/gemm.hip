@@ -1,5 +1,6 @@
 // Contraction GEMM: kernel instantiations, tile selection, autotuner and the
 // grouped launch used for uneven batches of small problems.
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -26,7 +27,7 @@ static const Cfg kCfgs[] = {
     {128, 128, 32, 2, 2, 0.95f}, {128, 64, 32, 2, 2, 0.70f},  {64, 128, 32, 2, 2, 0.70f},
     {64, 64, 32, 2, 2, 0.55f},   {32, 32, 32, 1, 1, 0.25f},  {160, 128, 16, 1, 4, 1.00f},
     {128, 160, 16, 4, 1, 1.00f},   {160, 256, 32, 1, 8, 2.00f}, {256, 160, 32, 8, 1, 2.00f},
-    {128, 160, 32, 4, 1, 1.60f, 2}, {160, 128, 32, 1, 4, 1.60f, 2},
+    {128, 160, 32, 4, 1, 1.60f, 2}, {160, 128, 32, 1, 4, 1.60f, 2}, {64, 64, 32, 2, 2, 0.45f, 2},
 };
 static constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -42,19 +43,23 @@ static int gemm_variant(const GemmDesc& d) {
 
 static GemmFn pick_fn(const GemmDesc& d, int prec, int cfg) { return gemm_fn_prec(prec, cfg, gemm_variant(d)); }
 
-// grouped configurations: 0 -> 128x128, 1 -> 64x64, 2 -> 32x32
-static const int kGroupedCfg[3] = {3, 6, 7};
+// grouped configurations: 0 -> 128x128, 1 -> 64x64, 2 -> 32x32, 3 -> 64x64 in two k-slices
+static const int kGroupedCfg[4] = {3, 6, 7, 14};
 int grouped_tile_m(int cfg) { return kCfgs[kGroupedCfg[cfg]].bm; }
 int grouped_tile_n(int cfg) { return kCfgs[kGroupedCfg[cfg]].bn; }
 
 static GroupedFn pick_grouped(int prec, int cfg, int variant) { return grouped_fn_prec(prec, cfg, variant); }
 
 static int g_forced_cfg = -1;
+static std::atomic<int> g_forced_grouped{-1};
 
-// eight-wave tiles have a fixed 256-register budget that the run-time-mode
-// gathers exceed: they serve the fast gathers only
+int forced_grouped_cfg() { return g_forced_grouped.load(); }
+
+// eight-wave tiles larger than 64 x 64 have a fixed 256-register budget that
+// the run-time-mode gathers exceed: they serve the fast gathers only
 static bool cfg_allowed(const GemmDesc& d, int c) {
-  return kCfgs[c].wm * kCfgs[c].wn * kCfgs[c].wk < 8 || gemm_variant(d) != 0;
+  const Cfg& g = kCfgs[c];
+  return g.wm * g.wn * g.wk < 8 || g.bm * g.bn <= 64 * 64 || gemm_variant(d) != 0;
 }
 
 static int heuristic_cfg(const GemmDesc& d) {
@@ -174,7 +179,7 @@ int32_t launch_gemm_grouped(const Gemm2D* dev_probs, const int32_t* dev_tile_sta
                             int32_t total_tiles, int32_t prec, int cfg, int variant, hipStream_t st) {
   if (n_probs <= 0 || total_tiles <= 0) return TN_OK;
   const Cfg& g = kCfgs[kGroupedCfg[cfg]];
-  hipLaunchKernelGGL(pick_grouped(prec, cfg, variant), dim3((unsigned)total_tiles), dim3(g.wm * g.wn * 64), 0, st, dev_probs,
+  hipLaunchKernelGGL(pick_grouped(prec, cfg, variant), dim3((unsigned)total_tiles), dim3(g.wm * g.wn * g.wk * 64), 0, st, dev_probs,
                      dev_tile_start, n_probs);
   return hip_check(hipGetLastError(), "grouped gemm launch");
 }
@@ -201,4 +206,10 @@ int32_t tn_tune_force_config(int32_t cfg) {
 }
 
 int32_t tn_tune_num_configs(void) { return tn::kNumCfgs; }
+
+int32_t tn_tune_force_grouped_config(int32_t cfg) {
+  if (cfg < -1 || cfg > 3) return tn::fail(TN_ERR_INVALID_ARGUMENT, "grouped tile config %d", cfg);
+  tn::g_forced_grouped.store(cfg);
+  return TN_OK;
+}
 }

@@ -40,10 +40,10 @@ __global__ void __launch_bounds__(WM* WN * WK * 64)
 // into a full descriptor held in LDS.
 // AMODE / BMODE as for gemm_kernel: the fast gathers when the host has
 // checked that every problem of the launch has those layouts, else -1.
-template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE = -1, int BMODE = -1>
-__global__ void __launch_bounds__(WM* WN * 64)
+template <int P, int BM, int BN, int BK, int WM, int WN, int AMODE = -1, int BMODE = -1, int WK = 1>
+__global__ void __launch_bounds__(WM* WN * WK * 64)
     gemm_grouped_kernel(const Gemm2D* probs, const int32_t* tile_start, int32_t n_probs) {
-  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::lds_bytes];
+  __shared__ __attribute__((aligned(16))) char smem[GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE, WK>::lds_bytes];
   __shared__ GemmDesc sd;
   __shared__ int32_t s_prob;
   const int bid = blockIdx.x;
@@ -97,7 +97,10 @@ __global__ void __launch_bounds__(WM* WN * 64)
     d.c_mode = (p.scm == 1 && p.M % 4 == 0 && p.scn % 4 == 0 && al(p.c)) ? STORE_MVEC : STORE_SCALAR;
   }
   __syncthreads();
-  GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE>::run(sd, sd.gk, bid - tile_start[s_prob], 0, smem);
+  // a tile table built for another tile size must not reach past the problem
+  const int tile = bid - tile_start[s_prob];
+  if (tile >= sd.tiles_m * sd.tiles_n) return;
+  GemmTile<P, BM, BN, BK, WM, WN, AMODE, BMODE, WK>::run(sd, sd.gk, tile, 0, smem);
 }
 
 
@@ -117,6 +120,7 @@ GemmFn gemm_fn_modes(int cfg) {
     case 11: return gemm_kernel<P, 256, 160, 32, 8, 1, AM, BM_>;
     case 12: return gemm_kernel<P, 128, 160, 32, 4, 1, AM, BM_, 2>;
     case 13: return gemm_kernel<P, 160, 128, 32, 1, 4, AM, BM_, 2>;
+    case 14: return gemm_kernel<P, 64, 64, 32, 2, 2, AM, BM_, 2>;
     default: return gemm_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }
@@ -138,6 +142,7 @@ GroupedFn grouped_fn_modes(int cfg) {
   switch (cfg) {
     case 0: return gemm_grouped_kernel<P, 128, 128, 32, 2, 2, AM, BM_>;
     case 1: return gemm_grouped_kernel<P, 64, 64, 32, 2, 2, AM, BM_>;
+    case 3: return gemm_grouped_kernel<P, 64, 64, 32, 2, 2, AM, BM_, 2>;
     default: return gemm_grouped_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }

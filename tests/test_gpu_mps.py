@@ -133,6 +133,30 @@ def test_inner_batched_aligned_bonds(prec):
         assert value_rel(got[i, 0], got[i, 1], mr, sr) <= 4 * TOL[prec], i
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_inner_batched_every_grouped_tile(tile, prec):
+    """Each grouped tile (128, 64, 32, 64 in two k-slices) on odd and aligned
+    bonds, with several tiles per problem and ragged edges."""
+    rng = np.random.default_rng(53)
+    chains, refs = [], []
+    for i, chi in enumerate([3, 17, 64, 97, 150, 200]):
+        n = int(rng.integers(5, 12))
+        psi, phi = inputs.uneven_chain(i, n, chi, seed=421)
+        psi, phi = r32(psi), r32(phi)
+        refs.append(oracle.mps_inner(psi, phi))
+        chains.append((g32(psi), g32(phi)))
+    try:
+        tn.tune_force_grouped_config(tile)
+        out = tn.mps_inner_batched(chains, prec=prec)
+        torch.cuda.synchronize()
+    finally:
+        tn.tune_force_grouped_config(-1)
+    got = out.cpu().numpy()
+    for i, (mr, sr) in enumerate(refs):
+        assert value_rel(got[i, 0], got[i, 1], mr, sr) <= 4 * TOL[prec], (tile, i)
+
+
 def test_inner_batched_sample_of_full_workload():
     """Eight chains drawn from the 512-chain uneven workload (N up to 256, chi up to 512)."""
     shapes = inputs.uneven_chain_shapes()
