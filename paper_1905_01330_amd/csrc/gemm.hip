@@ -27,7 +27,8 @@ static const Cfg kCfgs[] = {
     {128, 128, 32, 2, 2, 0.95f}, {128, 64, 32, 2, 2, 0.70f},  {64, 128, 32, 2, 2, 0.70f},
     {64, 64, 32, 2, 2, 0.55f},   {32, 32, 32, 1, 1, 0.25f},  {160, 128, 16, 1, 4, 1.00f},
     {128, 160, 16, 4, 1, 1.00f},   {160, 256, 32, 1, 8, 2.00f}, {256, 160, 32, 8, 1, 2.00f},
-    {128, 160, 32, 4, 1, 1.60f, 2}, {160, 128, 32, 1, 4, 1.60f, 2}, {64, 64, 32, 2, 2, 0.45f, 2},
+    {128, 160, 32, 4, 1, 1.60f, 2}, {160, 128, 32, 1, 4, 1.60f, 2}, {64, 64, 64, 2, 2, 0.45f, 2},
+    {64, 64, 64, 2, 2, 0.55f},
 };
 static constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -44,7 +45,7 @@ static int gemm_variant(const GemmDesc& d) {
 static GemmFn pick_fn(const GemmDesc& d, int prec, int cfg) { return gemm_fn_prec(prec, cfg, gemm_variant(d)); }
 
 // grouped configurations: 0 -> 128x128, 1 -> 64x64, 2 -> 32x32, 3 -> 64x64 in two k-slices
-static const int kGroupedCfg[4] = {3, 6, 7, 14};
+static const int kGroupedCfg[4] = {3, 15, 7, 14};
 int grouped_tile_m(int cfg) { return kCfgs[kGroupedCfg[cfg]].bm; }
 int grouped_tile_n(int cfg) { return kCfgs[kGroupedCfg[cfg]].bn; }
 

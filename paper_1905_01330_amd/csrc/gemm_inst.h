@@ -120,7 +120,8 @@ GemmFn gemm_fn_modes(int cfg) {
     case 11: return gemm_kernel<P, 256, 160, 32, 8, 1, AM, BM_>;
     case 12: return gemm_kernel<P, 128, 160, 32, 4, 1, AM, BM_, 2>;
     case 13: return gemm_kernel<P, 160, 128, 32, 1, 4, AM, BM_, 2>;
-    case 14: return gemm_kernel<P, 64, 64, 32, 2, 2, AM, BM_, 2>;
+    case 14: return gemm_kernel<P, 64, 64, 64, 2, 2, AM, BM_, 2>;
+    case 15: return gemm_kernel<P, 64, 64, 64, 2, 2, AM, BM_>;
     default: return gemm_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }
@@ -141,8 +142,8 @@ template <int P, int AM, int BM_>
 GroupedFn grouped_fn_modes(int cfg) {
   switch (cfg) {
     case 0: return gemm_grouped_kernel<P, 128, 128, 32, 2, 2, AM, BM_>;
-    case 1: return gemm_grouped_kernel<P, 64, 64, 32, 2, 2, AM, BM_>;
-    case 3: return gemm_grouped_kernel<P, 64, 64, 32, 2, 2, AM, BM_, 2>;
+    case 1: return gemm_grouped_kernel<P, 64, 64, 64, 2, 2, AM, BM_>;
+    case 3: return gemm_grouped_kernel<P, 64, 64, 64, 2, 2, AM, BM_, 2>;
     default: return gemm_grouped_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }

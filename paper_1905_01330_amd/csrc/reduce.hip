@@ -137,46 +137,74 @@ __global__ void __launch_bounds__(256) reduce_kernel(const ReduceDesc d) {
 }
 
 // mode 3: four consecutive outputs per thread (its own kernel, so the wider
-// registers do not lower the occupancy of the other modes)
+// registers do not lower the occupancy of the other modes).  KG > 1 splits
+// each output's k range over KG threads of the workgroup (k = kg, kg + KG,
+// ...) when the outputs alone give too few workgroups to keep the loads in
+// flight; the KG partial sums are then added in the fixed order kg = 0, 1, ...
+template <int KG>
 __global__ void __launch_bounds__(256) reduce4_kernel(const ReduceDesc d) {
+  constexpr int QPB = 256 / KG;   // quads of outputs per workgroup
+  __shared__ double part[KG > 1 ? KG : 1][QPB][4];
   const int in = d.gr.n - 1;
   const int64_t so = d.gr.s[2][in];
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.R / 4; q += nthreads) {
-    int64_t o[3];
-    group_offsets<3>(d.gr, (uint32_t)(4 * q), o, 0);
+  const int ql = threadIdx.x % QPB, kg = threadIdx.x / QPB;
+  const int64_t nq = d.R / 4;
+  for (int64_t base = (int64_t)blockIdx.x * QPB; base < nq; base += (int64_t)gridDim.x * QPB) {
+    const int64_t q = base + ql;
+    const bool valid = q < nq;
+    int64_t o[3] = {0, 0, 0};
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      group_offsets<3>(d.gr, (uint32_t)(4 * q), o, 0);
 #pragma unroll 4
-    for (int64_t k = 0; k < d.K; ++k) {
-      const float* xp = d.x + o[0] + k_offset(d.gk, 0, (uint32_t)k);
-      const float* yp = d.y ? d.y + o[1] + k_offset(d.gk, 1, (uint32_t)k) : nullptr;
-      f4_t xv, yv = {1.f, 1.f, 1.f, 1.f};
-      if ((reinterpret_cast<uintptr_t>(xp) & 15) == 0) {
-        xv = *reinterpret_cast<const f4_t*>(xp);
-      } else {
-        xv = f4_t{xp[0], xp[1], xp[2], xp[3]};
-      }
-      if (yp) {
-        if ((reinterpret_cast<uintptr_t>(yp) & 15) == 0)
-          yv = *reinterpret_cast<const f4_t*>(yp);
-        else
-          yv = f4_t{yp[0], yp[1], yp[2], yp[3]};
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float a = xv[j], b = yv[j];
-        if (d.bf16_round) {
-          a = bf16_rne(a);
-          b = bf16_rne(b);
+      for (int64_t k = kg; k < d.K; k += KG) {
+        const float* xp = d.x + o[0] + k_offset(d.gk, 0, (uint32_t)k);
+        const float* yp = d.y ? d.y + o[1] + k_offset(d.gk, 1, (uint32_t)k) : nullptr;
+        f4_t xv, yv = {1.f, 1.f, 1.f, 1.f};
+        if ((reinterpret_cast<uintptr_t>(xp) & 15) == 0) {
+          xv = *reinterpret_cast<const f4_t*>(xp);
+        } else {
+          xv = f4_t{xp[0], xp[1], xp[2], xp[3]};
         }
-        acc[j] += (double)a * (double)b;
+        if (yp) {
+          if ((reinterpret_cast<uintptr_t>(yp) & 15) == 0)
+            yv = *reinterpret_cast<const f4_t*>(yp);
+          else
+            yv = f4_t{yp[0], yp[1], yp[2], yp[3]};
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float a = xv[j], b = yv[j];
+          if (d.bf16_round) {
+            a = bf16_rne(a);
+            b = bf16_rne(b);
+          }
+          acc[j] += (double)a * (double)b;
+        }
       }
     }
-    if (so == 1 && (reinterpret_cast<uintptr_t>(d.out + o[2]) & 15) == 0) {
-      *reinterpret_cast<f4_t*>(d.out + o[2]) = f4_t{(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
-    } else {
+    if constexpr (KG > 1) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) d.out[o[2] + j * so] = (float)acc[j];
+      for (int j = 0; j < 4; ++j) part[kg][ql][j] = acc[j];
+      __syncthreads();
+      if (kg == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          double t = part[0][ql][j];
+#pragma unroll
+          for (int g = 1; g < KG; ++g) t += part[g][ql][j];
+          acc[j] = t;
+        }
+      }
+      __syncthreads();
+    }
+    if (valid && kg == 0) {
+      if (so == 1 && (reinterpret_cast<uintptr_t>(d.out + o[2]) & 15) == 0) {
+        *reinterpret_cast<f4_t*>(d.out + o[2]) = f4_t{(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d.out[o[2] + j * so] = (float)acc[j];
+      }
     }
   }
 }
@@ -218,11 +246,23 @@ __global__ void __launch_bounds__(256) elementwise4_kernel(const ReduceDesc d) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += nthreads) {
     int64_t o[3];
     group_offsets<3>(d.gr, (uint32_t)(4 * q), o, 0);
+    // the four inputs of each operand: one load when its stride is 0 (the
+    // operand does not carry the innermost output axis), one 16-byte load
+    // when it is 1 and aligned, else four
+    auto four = [](const float* p, int64_t s) {
+      if (s == 0) {
+        const float t = *p;
+        return f4_t{t, t, t, t};
+      }
+      if (s == 1 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) return *reinterpret_cast<const f4_t*>(p);
+      return f4_t{p[0], p[s], p[2 * s], p[3 * s]};
+    };
+    const f4_t xq = four(d.x + o[0], sx);
+    const f4_t yq = d.y ? four(d.y + o[1], sy) : f4_t{1.f, 1.f, 1.f, 1.f};
     f4_t v;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float xv = d.x[o[0] + j * sx];
-      float yv = d.y ? d.y[o[1] + j * sy] : 1.0f;
+      float xv = xq[j], yv = yq[j];
       if (d.bf16_round) {
         xv = bf16_rne(xv);
         yv = bf16_rne(yv);
@@ -230,7 +270,8 @@ __global__ void __launch_bounds__(256) elementwise4_kernel(const ReduceDesc d) {
       v[j] = (float)((double)xv * (double)yv);
     }
     if ((reinterpret_cast<uintptr_t>(d.out + o[2]) & 15) == 0) {
-      *reinterpret_cast<f4_t*>(d.out + o[2]) = v;
+      // streamed: the product is written once and not read back here
+      __builtin_nontemporal_store(v, reinterpret_cast<f4_t*>(d.out + o[2]));
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j) d.out[o[2] + j] = v[j];
@@ -287,14 +328,19 @@ int32_t launch_reduce(ReduceDesc& d, void* scratch, size_t scratch_bytes, hipStr
     blocks = (d.R + 255) / 256;
   else if (d.mode == 3)
     blocks = (d.R / 4 + 255) / 256;
+  // few workgroups of outputs and a k range worth splitting: four threads per output quad
+  const bool ksplit = d.mode == 3 && blocks < 1024 && d.K >= 16;
+  if (ksplit) blocks = (d.R / 4 + 63) / 64;
   else if (d.mode == 1)
     blocks = (d.R + 3) / 4;
   else
     blocks = d.R;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  if (d.mode == 3)
-    hipLaunchKernelGGL(reduce4_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d);
+  if (d.mode == 3 && ksplit)
+    hipLaunchKernelGGL(reduce4_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, d);
+  else if (d.mode == 3)
+    hipLaunchKernelGGL(reduce4_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, d);
   else
     hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d);
   return hip_check(hipGetLastError(), "reduce launch");
