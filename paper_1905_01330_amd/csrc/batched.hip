@@ -84,6 +84,9 @@ bool is_contiguous(const tn_tensor& t) {
 // total work: the estimate is, in units of one wave's 32 x 32 block times one
 // k, the larger of the longest wave's work and the total padded work spread
 // over the 1024 SIMDs, divided by a per-wave efficiency of the tile shape.
+// The efficiencies are measured ones: on odd bond dimensions (run-time
+// gathers) the k-sliced 64 x 64 tile was fastest at every batch size tried,
+// the 128 x 128 tile slowest.
 //   0: 128 x 128 (four 64 x 64 waves)   1: 64 x 64 (four 32 x 32 waves)
 //   3: 64 x 64 in two k-slices (eight waves, each over half of K)
 //   2: 32 x 32 when every problem of the step fits one such tile
@@ -96,7 +99,7 @@ int step_cfg(const std::vector<Gemm2D>& v) {
     double per_wave;  // blocks x k per wave, per k of the problem
     double eff;
   };
-  static const Cand cands[] = {{0, 128, 4.0, 1.0}, {1, 64, 1.0, 0.7}, {3, 64, 0.5, 0.6}};
+  static const Cand cands[] = {{0, 128, 4.0, 0.6}, {1, 64, 1.0, 0.8}, {3, 64, 0.5, 1.0}};
   int best = 0;
   double best_t = 1e300;
   for (const Cand& c : cands) {

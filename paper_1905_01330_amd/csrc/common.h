@@ -52,8 +52,8 @@ __host__ __device__ inline void group_offsets(const Group& g, uint32_t idx, int6
 
 // Contraction GEMM descriptor: C[m, n] = sum_k A[m, k] B[k, n] over strided views.
 //   gm: strides (A, C, -)   gn: strides (B, C, -)   gk: strides (A, B, -)
-// LOAD_MNSCALAR: rows unit-stride (in runs of four) but not 16-byte loadable:
-// the 4-row micro-blocks of LOAD_MNVEC assembled from scalar loads
+// LOAD_MNSCALAR: innermost row index unit-stride but not 16-byte loadable:
+// scalar loads with the lanes of a wavefront along the rows
 enum LoadMode : int32_t { LOAD_GENERIC = 0, LOAD_KVEC = 1, LOAD_MNVEC = 2, LOAD_MNSCALAR = 3 };
 enum StoreMode : int32_t { STORE_SCALAR = 0, STORE_MVEC = 1 };
 

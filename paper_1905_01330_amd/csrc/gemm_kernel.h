@@ -202,11 +202,11 @@ struct OperandLoader {
     scale = scale_;
     rowok = 0;
     const int tid = threadIdx.x;
-    if (mode != LOAD_MNVEC && mode != LOAD_MNSCALAR) {
+    if (mode != LOAD_MNVEC) {
 #pragma unroll
       for (int v = 0; v < VK; ++v) {
         int idx = tid + v * NT;
-        int row = row0 + idx / KQ;
+        int row = row0 + (mode == LOAD_MNSCALAR ? idx % R : idx / KQ);
         rowoff[v] = 0;
         if (idx < NKV && row < nrows) {
           int64_t o[1];
@@ -242,6 +242,21 @@ struct OperandLoader {
         if (((rowok >> v) & 1u) && k < K) x = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k));
         st[v] = x;
       }
+    } else if (mode == LOAD_MNSCALAR) {
+      // lanes run along the unit-stride rows: each load instruction reads
+      // 64 consecutive floats of one k
+#pragma unroll
+      for (int v = 0; v < VK; ++v) {
+        int idx = tid + v * NT;
+        int k = k0 + (idx / R) * 4;
+        f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+        if ((rowok >> v) & 1u) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (k + j < K) x[j] = base[rowoff[v] + koff(gk, k + j)];
+        }
+        st[v] = x;
+      }
     } else if (mode == LOAD_GENERIC) {
 #pragma unroll
       for (int v = 0; v < VK; ++v) {
@@ -268,24 +283,7 @@ struct OperandLoader {
         const int64_t ks = gk.s[KIDX][last];
         const bool ok = (rowok >> v) & 1u;
         f32x4_t x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0, x2 = x0, x3 = x0;
-        if (mode == LOAD_MNSCALAR) {
-          // rows r .. r+3 are consecutive addresses; rows past the end read 0
-          const int r = row0 + (idx / KQ) * 4;
-          auto col = [&](int kk) {
-            f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-            if (ok && kk < K) {
-              const float* p = base + rowoff[v] + koff(gk, kk);
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                if (r + i < nrows) x[i] = p[i];
-            }
-            return x;
-          };
-          x0 = col(k + 0);
-          x1 = col(k + 1);
-          x2 = col(k + 2);
-          x3 = col(k + 3);
-        } else if (run) {
+        if (run) {
           const float* p = base + rowoff[v] + ko;
           if (ok && k + 0 < K) x0 = *reinterpret_cast<const f32x4_t*>(p);
           if (ok && k + 1 < K) x1 = *reinterpret_cast<const f32x4_t*>(p + ks);
@@ -307,7 +305,13 @@ struct OperandLoader {
 
   __device__ __forceinline__ void store(char* lds) {
     const int tid = threadIdx.x;
-    if (mode != LOAD_MNVEC && mode != LOAD_MNSCALAR) {
+    if (mode == LOAD_MNSCALAR) {
+#pragma unroll
+      for (int v = 0; v < VK; ++v) {
+        int idx = tid + v * NT;
+        if (idx < NKV) lds_put4<P, R, BK>(lds, idx % R, (idx / R) * 4, st[v]);
+      }
+    } else if (mode != LOAD_MNVEC) {
 #pragma unroll
       for (int v = 0; v < VK; ++v) {
         int idx = tid + v * NT;

@@ -184,11 +184,9 @@ static bool vec4_ok(const Group& inner, int ti, const Group& other, int oi, cons
   return true;
 }
 
-// rows unit-stride, in runs of four that never straddle an outer index
+// innermost row index unit-stride: the gather reads along rows
 static bool mn_scalar_ok(const Group& rows, int ti) {
-  if (rows.n < 1) return false;
-  const int last = rows.n - 1;
-  return rows.s[ti][last] == 1 && (rows.n == 1 || rows.dim[last] % 4 == 0);
+  return rows.n >= 1 && rows.s[ti][rows.n - 1] == 1;
 }
 
 void choose_modes(GemmDesc& d) {
