@@ -84,9 +84,9 @@ bool is_contiguous(const tn_tensor& t) {
 // total work: the estimate is, in units of one wave's 32 x 32 block times one
 // k, the larger of the longest wave's work and the total padded work spread
 // over the 1024 SIMDs, divided by a per-wave efficiency of the tile shape.
-// The efficiencies are measured ones: on odd bond dimensions (run-time
-// gathers) the k-sliced 64 x 64 tile was fastest at every batch size tried,
-// the 128 x 128 tile slowest.
+// The efficiencies follow measurement on a batch of 32 chains with odd bond
+// dimensions (run-time gathers; N up to 256, chi up to 512): the k-sliced
+// 64 x 64 tile throughout was fastest, the 128 x 128 tile throughout slowest.
 //   0: 128 x 128 (four 64 x 64 waves)   1: 64 x 64 (four 32 x 32 waves)
 //   3: 64 x 64 in two k-slices (eight waves, each over half of K)
 //   2: 32 x 32 when every problem of the step fits one such tile
