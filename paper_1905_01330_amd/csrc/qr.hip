@@ -8,8 +8,9 @@
 // Up to 2048 rows the factorisation is blocked in the compact WY form
 // (Schreiber and Van Loan; Golub and Van Loan 5.2.3): a panel of 16 columns
 // is factorised by one workgroup holding the panel in registers (two
-// workgroup reductions per column), which then forms the panel's triangular
-// factor T from the Gram matrix of its reflectors; one launch applies
+// workgroup reductions per column, row conditions as selects so the unrolled
+// panel stays short), which then forms the panel's triangular factor T from
+// the Gram matrix of its reflectors; one launch applies
 // I - V T^T V^T to all trailing columns (one reduction per workgroup); Q is
 // accumulated panel by panel in reverse with I - V T V^T.
 // Taller matrices take one reflector launch and one update launch per column.
@@ -171,7 +172,8 @@ __device__ inline void qr_block_sum(double (&v)[NV], double (*red)[kQrWaves * 64
 
 // the reflector of panel column J (a template argument, so the register
 // panel is only indexed by constants), then its update of the panel columns
-// to its right; the same arithmetic as reflector_kernel + reflect_cols_kernel
+// to its right; the same arithmetic as reflector_kernel + reflect_cols_kernel.
+// Row conditions are selects, not branches, to keep the unrolled panel short.
 template <int J>
 __device__ __forceinline__ void qr_panel_step(double (&x)[kQrRows][kQrNb], double (*red)[kQrWaves * 64], int& buf,
                                               double* tau, int m, int j0, int nb) {
@@ -182,8 +184,9 @@ __device__ __forceinline__ void qr_panel_step(double (&x)[kQrRows][kQrNb], doubl
 #pragma unroll
       for (int q = 0; q < kQrRows; ++q) {
         const int row = threadIdx.x + kQrThreads * q;
-        if (row > gj && row < m) s[0] += x[q][J] * x[q][J];
-        if (row == gj) s[1] = x[q][J];
+        const double xv = x[q][J];
+        s[0] += (row > gj && row < m) ? xv * xv : 0.0;
+        s[1] += row == gj ? xv : 0.0;
       }
       qr_block_sum<2, 2>(s, red, buf);
       const double sigma = s[0], alpha = s[1];
@@ -195,34 +198,34 @@ __device__ __forceinline__ void qr_panel_step(double (&x)[kQrRows][kQrNb], doubl
 #pragma unroll
         for (int q = 0; q < kQrRows; ++q) {
           const int row = threadIdx.x + kQrThreads * q;
-          if (row > gj && row < m) x[q][J] *= scale;
-          if (row == gj) x[q][J] = beta;
+          const double xv = x[q][J];
+          x[q][J] = (row > gj && row < m) ? xv * scale : (row == gj ? beta : xv);
         }
       }
       if (threadIdx.x == 0) tau[gj] = t;
       if constexpr (J + 1 < kQrNb) {
+        // t is the same in every thread, so the barriers inside are reached by all
         if (t != 0.0 && J + 1 < nb) {
           constexpr int NW = kQrNb - J - 1;
+          double v[kQrRows];   // the reflector at this thread's rows: 1 at gj, X below, 0 above
+#pragma unroll
+          for (int q = 0; q < kQrRows; ++q) {
+            const int row = threadIdx.x + kQrThreads * q;
+            v[q] = (row > gj && row < m) ? x[q][J] : (row == gj ? 1.0 : 0.0);
+          }
           double w[NW];
 #pragma unroll
           for (int c = 0; c < NW; ++c) {
             w[c] = 0.0;
 #pragma unroll
-            for (int q = 0; q < kQrRows; ++q) {
-              const int row = threadIdx.x + kQrThreads * q;
-              if (row > gj && row < m) w[c] += x[q][J] * x[q][J + 1 + c];
-              if (row == gj) w[c] += x[q][J + 1 + c];
-            }
+            for (int q = 0; q < kQrRows; ++q) w[c] += v[q] * x[q][J + 1 + c];
           }
           qr_block_sum<NW, (NW > 8 ? 16 : NW > 4 ? 8 : NW > 2 ? 4 : NW > 1 ? 2 : 1)>(w, red, buf);
 #pragma unroll
           for (int c = 0; c < NW; ++c) {
+            const double tw = t * w[c];
 #pragma unroll
-            for (int q = 0; q < kQrRows; ++q) {
-              const int row = threadIdx.x + kQrThreads * q;
-              if (row > gj && row < m) x[q][J + 1 + c] -= t * w[c] * x[q][J];
-              if (row == gj) x[q][J + 1 + c] -= t * w[c];
-            }
+            for (int q = 0; q < kQrRows; ++q) x[q][J + 1 + c] -= tw * v[q];
           }
         }
       }
@@ -258,18 +261,28 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(double* xc, double
         if (c < nb) xc[(int64_t)(j0 + c) * m + row] = x[q][c];
     }
   }
-  // Gram entries v_i . v_j (i < j) of the reflectors: v_j is 1 at row
-  // j0 + j, x below it, 0 above; 120 pairs in batches of 32
+  // the reflectors in place of the panel: v_c is 1 at row j0 + c, X below it,
+  // 0 above (and 0 in the columns past nb)
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int row = threadIdx.x + kQrThreads * q;
+#pragma unroll
+    for (int c = 0; c < kQrNb; ++c) {
+      const int gc = j0 + c;
+      x[q][c] = (c >= nb || row >= m) ? 0.0 : (row == gc ? 1.0 : (row > gc ? x[q][c] : 0.0));
+    }
+  }
+  // Gram entries v_i . v_j (i < j), enumerated column by column: 120 pairs in
+  // batches of 16 (registers: the panel holds 128)
   constexpr int kPairs = kQrNb * (kQrNb - 1) / 2;
 #pragma unroll
-  for (int b0 = 0; b0 < kPairs; b0 += 32) {
-    double g[32];
+  for (int b0 = 0; b0 < kPairs; b0 += 16) {
+    double g[16];
 #pragma unroll
-    for (int p = 0; p < 32; ++p) {
+    for (int p = 0; p < 16; ++p) {
       g[p] = 0.0;
       const int pp = b0 + p;
       if (pp < kPairs) {
-        // pair index pp -> (i, j), i < j, enumerated column by column
         int j = 1, base = 0;
 #pragma unroll
         for (int jj = 1; jj < kQrNb; ++jj)
@@ -279,30 +292,17 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(double* xc, double
           }
         const int i = pp - base;
 #pragma unroll
-        for (int q = 0; q < kQrRows; ++q) {
-          const int row = threadIdx.x + kQrThreads * q;
-          const int gi = j0 + i, gjr = j0 + j;
-          double vi = 0.0, vj = 0.0;
-#pragma unroll
-          for (int c = 0; c < kQrNb; ++c) {
-            if (c == i) vi = row == gi ? 1.0 : (row > gi ? x[q][c] : 0.0);
-            if (c == j) vj = row == gjr ? 1.0 : (row > gjr ? x[q][c] : 0.0);
-          }
-          if (row < m && j < nb) g[p] += vi * vj;
-        }
+        for (int q = 0; q < kQrRows; ++q) g[p] += x[q][i] * x[q][j];
       }
     }
-    double r[32];
-#pragma unroll
-    for (int p = 0; p < 32; ++p) r[p] = g[p];
-    const double v = qr_reduce_scatter<32>(r);
+    const double v = qr_reduce_scatter<16>(g);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane < 32) red[buf][wave * 32 + lane] = v;
+    if (lane < 16) red[buf][wave * 16 + lane] = v;
     __syncthreads();
-    if (threadIdx.x < 32 && b0 + (int)threadIdx.x < kPairs) {
+    if (threadIdx.x < 16 && b0 + (int)threadIdx.x < kPairs) {
       double t = 0.0;
 #pragma unroll
-      for (int wv = 0; wv < kQrWaves; ++wv) t += red[buf][wv * 32 + threadIdx.x];
+      for (int wv = 0; wv < kQrWaves; ++wv) t += red[buf][wv * 16 + threadIdx.x];
       gram[b0 + threadIdx.x] = t;   // packed pair order
     }
     buf ^= 1;
