@@ -155,12 +155,16 @@ int32_t tn_network_order(int32_t n_nodes, const tn_tensor* nodes, const int32_t*
 
 /* ---------------------------------------------------------------------
  * MPS inner product <psi|phi> (the chain network of Fig. 3a, contracted
- * site by site from the left).  psi[k], phi[k] are TN_F32 [D_k, d, D_{k+1}]
- * with D_0 = D_N = 1 (the two chains may have different bond dims but the
- * same d).  Result written to out2 (DEVICE, 2 doubles): out2[0] = mantissa
- * m, out2[1] = log-scale s, value = m * exp(s).  After every site the
+ * site by site).  psi[k], phi[k] are TN_F32 [D_k, d, D_{k+1}] with
+ * D_0 = D_N = 1 (the two chains may have different bond dims but the same
+ * d).  Result written to out2 (DEVICE, 2 doubles): out2[0] = mantissa m,
+ * out2[1] = log-scale s, value = m * exp(s).  After every site the
  * environment is rescaled by a power of two (exact) and the exponent is
- * summed in FP64.
+ * summed in FP64.  Chains of 4 or more sites are contracted from both ends
+ * at once: the right half runs on a library-owned side stream (one per
+ * device, default priority) forked from and joined back into `stream`, so
+ * the call stays ordered on `stream` and can be recorded in a HIP graph;
+ * the halves meet in an FP64 sum over the middle bond (m then in [0.5, 1)).
  * ------------------------------------------------------------------- */
 int32_t tn_mps_inner_workspace(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi,
                                size_t* bytes);

@@ -1,9 +1,10 @@
 // Chain networks of Fig. 3a: MPS inner products (single and uneven batches)
 // and MPS-MPO-MPS environment sweeps.  Every site is a short sequence of
-// contraction GEMMs on the caller's stream; the inner product keeps its
-// running environment in range with exact power-of-two rescaling fused into
-// the GEMMs (the epilogue records max|E| with an atomic max, the next site's
-// operand gather multiplies by 2^-e) and sums the exponents in FP64.
+// contraction GEMMs; the inner product keeps its running environment in
+// range with exact power-of-two rescaling fused into the GEMMs (the epilogue
+// records max|E| with an atomic max, the next site's GEMM scales its result
+// by 2^-e) and sums the exponents in FP64.  A single inner product of 4 or
+// more sites runs its two halves from both ends on two streams.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -41,6 +42,53 @@ __global__ void mps_finish_kernel(const float* e_final, const uint32_t* slots, i
     double t = part[0] + part[1] + part[2] + part[3];
     out2[0] = (double)e_final[0];
     out2[1] = t * 0.69314718055994530942;
+  }
+}
+
+// Two-sided inner product: the left environment E_L at the middle bond and
+// the right one E_R meet in <psi|phi> = sum_{a', a} E_L[a', a] E_R[a', a].
+// Products of FP32 values are exact in FP64, so the FP64 sum needs neither
+// environment's last scale; partial sums per workgroup, then a fixed-order
+// total (deterministic).
+__global__ void __launch_bounds__(256) env_dot_partial_kernel(const float* __restrict__ el,
+                                                              const float* __restrict__ er, int64_t n, double* part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += (double)el[i] * (double)er[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// value = total * 2^(exponents applied on both sides), written as a mantissa
+// in [0.5, 1) and a natural-log scale
+__global__ void __launch_bounds__(256) env_dot_finish_kernel(const double* part, int n_part, const uint32_t* ls, int nl,
+                                                             const uint32_t* rsl, int nr, double* out2) {
+  __shared__ double red[2][4];
+  double v = threadIdx.x < n_part ? part[threadIdx.x] : 0.0;
+  double e = 0.0;
+  for (int i = threadIdx.x; i < nl; i += 256) e += (double)scale_exponent(ls[i]);
+  for (int i = threadIdx.x; i < nr; i += 256) e += (double)scale_exponent(rsl[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    v += __shfl_xor(v, o, 64);
+    e += __shfl_xor(e, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = v;
+    red[1][threadIdx.x >> 6] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double total = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double ex = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    int e2 = 0;
+    const double m = frexp(total, &e2);
+    out2[0] = m;
+    out2[1] = (ex + (double)e2) * 0.69314718055994530942;
   }
 }
 
@@ -92,8 +140,34 @@ static int32_t inner_site(const tn_tensor& psi, const tn_tensor& phi, float* e_i
   return launch_gemm(g, prec, st);
 }
 
+// right-to-left site of the two-sided inner product
+//   T[a', s, b] = sum_b' psi[a', s, b'] E_R[b', b]   (scaled by 2^-e of in_slot:
+//                                                      exact, so which factor carries it is immaterial)
+//   E_R'[a', a] = sum_{s, b} T[a', s, b] phi[a, s, b]
+static int32_t inner_site_right(const tn_tensor& psi, const tn_tensor& phi, float* e_in, float* e_out, float* t,
+                                uint32_t* in_slot, uint32_t* out_slot, int32_t prec, hipStream_t st) {
+  const int64_t da = psi.shape[0], db = phi.shape[0], d = psi.shape[1];
+  const int64_t da2 = psi.shape[2], db2 = phi.shape[2];
+  tn_tensor e = make_view(e_in, TN_F32, {da2, db2});
+  tn_tensor tv = make_view(t, TN_F32, {da, d, db2});
+  tn_tensor eo = make_view(e_out, TN_F32, {da, db});
+  const int32_t a1[1] = {2}, b1[1] = {0};
+  GemmDesc g;
+  TN_TRY(plan_gemm(psi, e, 1, a1, b1, tv, g));
+  g.a_scale_bits = in_slot;
+  TN_TRY(launch_gemm(g, prec, st));
+  const int32_t a2[2] = {1, 2}, b2[2] = {1, 2};
+  TN_TRY(plan_gemm(tv, phi, 2, a2, b2, eo, g));
+  g.c_absmax = out_slot;
+  return launch_gemm(g, prec, st);
+}
+
+// chains of at least this many sites are contracted from both ends at once
+constexpr int kInnerTwoSided = 4;
+constexpr int kEnvDotParts = 256;
+
 struct InnerLayout {
-  size_t e0, e1, t, slots, total;
+  size_t e0, e1, t, slots, er0, er1, tr, rslots, part, total;
 };
 
 static InnerLayout inner_layout(int32_t n, const std::vector<int64_t>& dp, const std::vector<int64_t>& dq, int64_t d) {
@@ -105,7 +179,12 @@ static InnerLayout inner_layout(int32_t n, const std::vector<int64_t>& dp, const
   L.e1 = align256(me * 4);
   L.t = L.e1 + align256(me * 4);
   L.slots = L.t + align256(mt * 4);
-  L.total = L.slots + align256((size_t)(n + 1) * 4);
+  L.er0 = L.slots + align256((size_t)(n + 1) * 4);
+  L.er1 = L.er0 + align256(me * 4);
+  L.tr = L.er1 + align256(me * 4);
+  L.rslots = L.tr + align256(mt * 4);
+  L.part = L.rslots + align256((size_t)(n + 1) * 4);
+  L.total = L.part + align256(kEnvDotParts * 8);
   return L;
 }
 
@@ -427,10 +506,52 @@ int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi
   float* e[2] = {reinterpret_cast<float*>(ws + L.e0), reinterpret_cast<float*>(ws + L.e1)};
   float* t = reinterpret_cast<float*>(ws + L.t);
   uint32_t* slots = reinterpret_cast<uint32_t*>(ws + L.slots);
-  hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(n_sites + 1)), dim3(256), 0, st, e[0], slots, n_sites + 1);
-  TN_TRY(hip_check(hipGetLastError(), "mps init"));
-  for (int k = 0; k < n_sites; ++k) TN_TRY(inner_site(psi[k], phi[k], e[k & 1], e[(k + 1) & 1], t, slots, k, prec, st));
-  hipLaunchKernelGGL(mps_finish_kernel, dim3(1), dim3(256), 0, st, e[n_sites & 1], slots, n_sites, out2);
+  if (n_sites < kInnerTwoSided) {
+    hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(n_sites + 1)), dim3(256), 0, st, e[0], slots, n_sites + 1);
+    TN_TRY(hip_check(hipGetLastError(), "mps init"));
+    for (int k = 0; k < n_sites; ++k) TN_TRY(inner_site(psi[k], phi[k], e[k & 1], e[(k + 1) & 1], t, slots, k, prec, st));
+    hipLaunchKernelGGL(mps_finish_kernel, dim3(1), dim3(256), 0, st, e[n_sites & 1], slots, n_sites, out2);
+    return hip_check(hipGetLastError(), "mps finish");
+  }
+  // Two-sided: sites 0 .. c-1 from the left on the caller's stream, sites
+  // n-1 .. c from the right on a side stream forked from it and joined back
+  // (capturable), issued site by site so both streams always have work.
+  // Each half is a chain of dependent GEMMs that alone leaves most of the
+  // chip idle at chi <= 1024; the two halves overlap.
+  const int c = n_sites / 2, nr = n_sites - c;
+  float* er[2] = {reinterpret_cast<float*>(ws + L.er0), reinterpret_cast<float*>(ws + L.er1)};
+  float* tr = reinterpret_cast<float*>(ws + L.tr);
+  uint32_t* rslots = reinterpret_cast<uint32_t*>(ws + L.rslots);   // rslots[i]: E_R at bond n - i
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  hipStream_t rs = st;
+  TN_TRY(side_stream(rs));
+  hipEvent_t fork = nullptr, join = nullptr;
+  TN_TRY(hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "create event"));
+  if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+    hipEventDestroy(fork);
+    return fail(TN_ERR_DEVICE, "create event failed");
+  }
+  hipEventRecord(fork, st);
+  hipStreamWaitEvent(rs, fork, 0);
+  hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(c + 1)), dim3(256), 0, st, e[0], slots, c + 1);
+  hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(nr + 1)), dim3(256), 0, rs, er[0], rslots, nr + 1);
+  int32_t rc = hip_check(hipGetLastError(), "mps init");
+  for (int i = 0; i < std::max(c, nr) && rc == TN_OK; ++i) {
+    if (i < c) rc = inner_site(psi[i], phi[i], e[i & 1], e[(i + 1) & 1], t, slots, i, prec, st);
+    if (rc == TN_OK && i < nr) {
+      const int k = n_sites - 1 - i;
+      rc = inner_site_right(psi[k], phi[k], er[i & 1], er[(i + 1) & 1], tr, rslots + i, rslots + i + 1, prec, rs);
+    }
+  }
+  hipEventRecord(join, rs);
+  hipStreamWaitEvent(st, join, 0);
+  hipEventDestroy(fork);
+  hipEventDestroy(join);
+  TN_TRY(rc);
+  const int64_t cnt = dp[c] * dq[c];
+  const int64_t parts = std::min<int64_t>(kEnvDotParts, (cnt + 255) / 256);
+  hipLaunchKernelGGL(env_dot_partial_kernel, dim3((unsigned)parts), dim3(256), 0, st, e[c & 1], er[nr & 1], cnt, part);
+  hipLaunchKernelGGL(env_dot_finish_kernel, dim3(1), dim3(256), 0, st, part, (int)parts, slots, c, rslots, nr, out2);
   return hip_check(hipGetLastError(), "mps finish");
 }
 

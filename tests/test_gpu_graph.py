@@ -98,3 +98,15 @@ def test_contraction_graph_with_permuted_output():
     expected = [base.clone()]
     g = tn.Graph(lambda: tn.contract_between(a, b, [2], [0], out=out, prec="split_bf16"))
     replay_and_check(g, [base], expected)
+
+
+def test_two_sided_inner_graph():
+    """A single inner product of 4+ sites forks its right half onto the
+    library's side stream and joins it back: both halves must be recorded."""
+    n, chi = 12, 48
+    psi = [torch.tensor(x, dtype=torch.float32, device=DEV) for x in inputs.random_mps(n, 2, chi, 21)]
+    phi = [torch.tensor(x, dtype=torch.float32, device=DEV) for x in inputs.random_mps(n, 2, chi, 22)]
+    expected = [tn.mps_inner(psi, phi, prec="split_bf16").clone()]
+    torch.cuda.synchronize()
+    g = tn.Graph(lambda: tn.mps_inner(psi, phi, prec="split_bf16"))
+    replay_and_check(g, [g.result], expected)

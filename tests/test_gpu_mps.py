@@ -83,6 +83,19 @@ def test_inner_rescaling_over_long_chain():
     assert value_rel(m, s, mr, sr) <= 2e-5
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7])
+def test_inner_short_and_odd_chains(n):
+    """Below four sites the chain runs from the left only; from four on the
+    halves run from both ends and meet at bond n // 2 (odd n: unequal halves)."""
+    psi = r32(inputs.random_mps(n, 2, 8, 500 + n))
+    phi = r32(inputs.random_mps(n, 2, 8, 600 + n))
+    mr, sr = oracle.mps_inner(psi, phi)
+    m, s = ms(tn.mps_inner(g32(psi), g32(phi)))
+    npsi = math.sqrt(oracle.mps_inner_value(psi, psi))
+    nphi = math.sqrt(oracle.mps_inner_value(phi, phi))
+    assert abs(m * math.exp(s) - mr * math.exp(sr)) / (npsi * nphi) <= TOL["fp32"]
+
+
 def test_inner_product_state_norm_one():
     rng = np.random.default_rng(3)
     n = 40
