@@ -174,8 +174,11 @@ int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi
 /* Many independent inner products in one call (chains of uneven length and
  * bond dimension).  psi_sites/phi_sites hold all chains' sites back to back;
  * chain c owns sites [site_offsets[c], site_offsets[c+1]).  out2 is DEVICE,
- * 2 doubles per chain.  Chains advance together, one site per step, as a
- * grouped GEMM over all chains still active. */
+ * 2 doubles per chain (mantissa, log scale, as for tn_mps_inner).  Chains
+ * of 4 or more sites are contracted from both ends at once; all chains
+ * advance together, one site per step and end, as grouped GEMMs over every
+ * half still active, and each chain's halves meet in an FP64 sum over its
+ * middle bond. */
 int32_t tn_mps_inner_batched_workspace(int32_t n_chains, const int32_t* site_offsets,
                                        const tn_tensor* psi_sites, const tn_tensor* phi_sites,
                                        size_t* bytes);

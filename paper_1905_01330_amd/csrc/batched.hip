@@ -1,9 +1,11 @@
-// Uneven batch of MPS inner products in one call.  All chains advance one
-// site per step; each step is two grouped GEMM launches (ket site into the
-// environment, then the bra site) over every chain still active, with the
-// problems of a launch described by a compact table in the workspace.  Within
-// a launch the problems are ordered by size, largest first, so the longest
-// tiles start earliest.  Problems are binned into three tile sizes.
+// Uneven batch of MPS inner products in one call.  Chains of four or more
+// sites are contracted from both ends at once (sites 0 .. c-1 from the left,
+// n-1 .. c from the right, c = n / 2), so the number of steps is half the
+// longest chain.  Every step is two grouped GEMM launches (ket site into the
+// environments, then the bra site) over the left and right halves still
+// active, with the problems of a launch described by a compact table in the
+// workspace, largest first so the longest tiles start earliest.  At the end
+// each chain's two environments meet in an FP64 sum over its middle bond.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -16,18 +18,25 @@ namespace tn {
 static size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct ChainRec {
-  float* e[2];
-  uint32_t* slots;
-  int32_t n;
-  int32_t pad;
+  float* e[2];        // left environments (in turn)
+  float* er[2];       // right environments
+  uint32_t* slots;    // left scales: slots[j] for bond j
+  uint32_t* rslots;   // right scales: rslots[i] for bond n - i
+  int32_t n;          // sites
+  int32_t c;          // middle bond: sites 0 .. c-1 from the left, n-1 .. c from the right
+  int64_t cnt;        // elements of either environment at bond c
 };
 
 __global__ void batched_init_kernel(const ChainRec* chains, int n_chains) {
   const int c = blockIdx.x;
   if (c >= n_chains) return;
   const ChainRec r = chains[c];
-  for (int i = threadIdx.x; i <= r.n; i += blockDim.x) r.slots[i] = i == 0 ? 0x3f800000u : 0u;
-  if (threadIdx.x == 0) r.e[0][0] = 1.0f;
+  for (int i = threadIdx.x; i <= r.c; i += blockDim.x) r.slots[i] = i == 0 ? 0x3f800000u : 0u;
+  for (int i = threadIdx.x; i <= r.n - r.c; i += blockDim.x) r.rslots[i] = i == 0 ? 0x3f800000u : 0u;
+  if (threadIdx.x == 0) {
+    r.e[0][0] = 1.0f;
+    r.er[0][0] = 1.0f;
+  }
 }
 
 __device__ inline int slot_exponent(uint32_t bits) {
@@ -36,17 +45,37 @@ __device__ inline int slot_exponent(uint32_t bits) {
   return e - 127;
 }
 
-__global__ void batched_finish_kernel(const ChainRec* chains, int n_chains, double* out2) {
+// one workgroup per chain: sum_{a', a} E_L[a', a] E_R[a', a] at the middle
+// bond in FP64 (products of FP32 values are exact), times 2^(the exponents
+// applied on both sides), written as a mantissa in [0.5, 1) and a log scale
+__global__ void __launch_bounds__(256) batched_finish_kernel(const ChainRec* chains, int n_chains, double* out2) {
+  __shared__ double red[2][4];
   const int c = blockIdx.x;
   if (c >= n_chains) return;
   const ChainRec r = chains[c];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < r.n; i += 64) s += (double)slot_exponent(r.slots[i]);
+  const float* el = r.e[r.c & 1];
+  const float* er = r.er[(r.n - r.c) & 1];
+  double v = 0.0, s = 0.0;
+  for (int64_t i = threadIdx.x; i < r.cnt; i += 256) v += (double)el[i] * (double)er[i];
+  for (int i = threadIdx.x; i < r.c; i += 256) s += (double)slot_exponent(r.slots[i]);
+  for (int i = threadIdx.x; i < r.n - r.c; i += 256) s += (double)slot_exponent(r.rslots[i]);
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  for (int o = 32; o >= 1; o >>= 1) {
+    v += __shfl_xor(v, o, 64);
+    s += __shfl_xor(s, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = v;
+    red[1][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    out2[2 * c] = (double)r.e[r.n & 1][0];
-    out2[2 * c + 1] = s * 0.69314718055994530942;
+    const double total = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double ex = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    int e2 = 0;
+    const double m = frexp(total, &e2);
+    out2[2 * c] = m;
+    out2[2 * c + 1] = (ex + (double)e2) * 0.69314718055994530942;
   }
 }
 
@@ -90,6 +119,9 @@ bool is_contiguous(const tn_tensor& t) {
 //   0: 128 x 128 (four 64 x 64 waves)   1: 64 x 64 (four 32 x 32 waves)
 //   3: 64 x 64 in two k-slices (eight waves, each over half of K)
 //   2: 32 x 32 when every problem of the step fits one such tile
+// chains of at least this many sites are contracted from both ends
+constexpr int kTwoSided = 4;
+
 int step_cfg(const std::vector<Gemm2D>& v) {
   bool tiny = true;
   for (const Gemm2D& q : v) tiny = tiny && q.M <= 32 && q.N <= 32;
@@ -127,11 +159,9 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
   std::vector<int64_t> phys(n_chains);
   std::vector<size_t> ebytes(n_chains), tbytes(n_chains);
   size_t chain_total = 0;
-  int max_n = 0;
   for (int c = 0; c < n_chains; ++c) {
     const int n = off[c + 1] - off[c];
     if (n < 1) return fail(TN_ERR_INVALID_ARGUMENT, "chain %d has no sites", c);
-    max_n = std::max(max_n, n);
     for (int k = 0; k < n; ++k) {
       const tn_tensor& a = psi[off[c] + k];
       const tn_tensor& b = phi[off[c] + k];
@@ -159,35 +189,86 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
     for (int k = 0; k < n; ++k) mt = std::max(mt, dp[c][k] * phys[c] * dq[c][k + 1]);
     ebytes[c] = align256b(me * 4);
     tbytes[c] = align256b(mt * 4);
-    chain_total += 2 * ebytes[c] + tbytes[c] + align256b((size_t)(n + 1) * 4);
+    chain_total += 4 * ebytes[c] + 2 * tbytes[c] + 2 * align256b((size_t)(n + 1) * 4);
   }
   // problem tables
   std::vector<int> order(n_chains);
   std::iota(order.begin(), order.end(), 0);
   P.chains.resize(n_chains);
   size_t o = 0;
-  std::vector<float*> tbuf(n_chains);
+  std::vector<float*> tbuf(n_chains), trbuf(n_chains);
+  int max_steps = 0;
   for (int c = 0; c < n_chains; ++c) {
     ChainRec& r = P.chains[c];
-    r.e[0] = reinterpret_cast<float*>(ws + o);
-    o += ebytes[c];
-    r.e[1] = reinterpret_cast<float*>(ws + o);
-    o += ebytes[c];
+    for (int h = 0; h < 2; ++h) {
+      r.e[h] = reinterpret_cast<float*>(ws + o);
+      o += ebytes[c];
+    }
+    for (int h = 0; h < 2; ++h) {
+      r.er[h] = reinterpret_cast<float*>(ws + o);
+      o += ebytes[c];
+    }
     tbuf[c] = reinterpret_cast<float*>(ws + o);
     o += tbytes[c];
-    r.slots = reinterpret_cast<uint32_t*>(ws + o);
+    trbuf[c] = reinterpret_cast<float*>(ws + o);
+    o += tbytes[c];
     r.n = off[c + 1] - off[c];
-    r.pad = 0;
+    r.c = r.n < kTwoSided ? r.n : r.n / 2;
+    r.cnt = dp[c][r.c] * dq[c][r.c];
+    r.slots = reinterpret_cast<uint32_t*>(ws + o);
     o += align256b((size_t)(r.n + 1) * 4);
+    r.rslots = reinterpret_cast<uint32_t*>(ws + o);
+    o += align256b((size_t)(r.n + 1) * 4);
+    max_steps = std::max(max_steps, std::max(r.c, r.n - r.c));
   }
   P.chain_bytes = o;
   const int forced = forced_grouped_cfg();
-  for (int j = 0; j < max_n; ++j) {
+  for (int j = 0; j < max_steps; ++j) {
     for (int g = 0; g < 2; ++g) {
       std::vector<std::pair<int64_t, Gemm2D>> v;
       for (int c = 0; c < n_chains; ++c) {
-        const int n = off[c + 1] - off[c];
-        if (j >= n) continue;
+        const ChainRec& r = P.chains[c];
+        if (j >= r.n - r.c) continue;
+        // right half: site k = n-1-j, E_R at bond k+1 in er[j & 1]
+        const int k = r.n - 1 - j;
+        const tn_tensor& a = psi[off[c] + k];
+        const tn_tensor& b = phi[off[c] + k];
+        const int64_t da = dp[c][k], da2 = dp[c][k + 1], d = phys[c], db = dq[c][k], db2 = dq[c][k + 1];
+        Gemm2D q;
+        std::memset(&q, 0, sizeof(q));
+        if (g == 0) {  // T[(a' s), b] = sum_b' psi[(a' s), b'] E_R[b', b]  (scaled by 2^-e: exact)
+          q.a = static_cast<const float*>(a.data);
+          q.b = r.er[j & 1];
+          q.c = trbuf[c];
+          q.M = (int32_t)(da * d);
+          q.K = (int32_t)da2;
+          q.N = (int32_t)db2;
+          q.sam = da2;
+          q.sak = 1;
+          q.sbk = db2;
+          q.sbn = 1;
+          q.scm = db2;
+          q.scn = 1;
+          q.a_scale_bits = r.rslots + j;
+        } else {  // E_R'[a', a] = sum_{(s b)} T[a', (s b)] phi[a, (s b)]
+          q.a = trbuf[c];
+          q.b = static_cast<const float*>(b.data);
+          q.c = r.er[(j + 1) & 1];
+          q.M = (int32_t)da;
+          q.K = (int32_t)(d * db2);
+          q.N = (int32_t)db;
+          q.sam = d * db2;
+          q.sak = 1;
+          q.sbk = 1;
+          q.sbn = d * db2;
+          q.scm = db;
+          q.scn = 1;
+          q.c_absmax = r.rslots + j + 1;
+        }
+        v.push_back({(int64_t)q.M * q.N * q.K, q});
+      }
+      for (int c = 0; c < n_chains; ++c) {
+        if (j >= P.chains[c].c) continue;
         const tn_tensor& a = psi[off[c] + j];
         const tn_tensor& b = phi[off[c] + j];
         const int64_t pa = dp[c][j], qa = dq[c][j], d = phys[c], pb = dp[c][j + 1], qb = dq[c][j + 1];
@@ -319,7 +400,7 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   for (const Launch& L : Q.launches)
     TN_TRY(launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off, L.n_probs, L.tiles, prec, L.cfg, L.variant,
                                st));
-  hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains, out2);
+  hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(256), 0, st, d_chains, n_chains, out2);
   return hip_check(hipGetLastError(), "batched finish");
 }
 
