@@ -96,6 +96,22 @@ def test_inner_short_and_odd_chains(n):
     assert abs(m * math.exp(s) - mr * math.exp(sr)) / (npsi * nphi) <= TOL["fp32"]
 
 
+def test_inner_exactly_zero():
+    """Orthogonal product states (bond dimension 1): the middle-bond sum is an
+    exact zero, which the mantissa/scale form must carry as m = 0."""
+    n = 6
+    zero = [np.array([1.0, 0.0]).reshape(1, 2, 1) for _ in range(n)]
+    one = [x.copy() for x in zero]
+    one[3] = np.array([0.0, 1.0]).reshape(1, 2, 1)
+    for prec in ("fp32", "split_bf16"):
+        m, s = ms(tn.mps_inner(g32(zero), g32(one), prec=prec))
+        assert m == 0.0 and np.isfinite(s)
+        m, s = ms(tn.mps_inner(g32(zero), g32(zero), prec=prec))
+        assert abs(m * math.exp(s) - 1.0) < 1e-12
+    out = tn.mps_inner_batched([(g32(zero), g32(one)), (g32(zero), g32(zero))]).cpu().numpy()
+    assert out[0, 0] == 0.0 and abs(out[1, 0] * math.exp(out[1, 1]) - 1.0) < 1e-12
+
+
 def test_inner_product_state_norm_one():
     rng = np.random.default_rng(3)
     n = 40
