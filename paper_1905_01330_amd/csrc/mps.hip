@@ -332,6 +332,88 @@ __global__ void __launch_bounds__(256) wstep_right_fixed(const float* __restrict
     }
 }
 
+// The left MPO step writing T2 with the pair (a', t) innermost: memory order
+// [v, b, a', t], so the GEMM that contracts it with A_k over (a', t) reads
+// that operand along k (16-byte loads, no transpose in registers).  A
+// workgroup computes 16 a' x 64 b for every (t, v) from coalesced T1 rows,
+// stages them in LDS (rows of 33 floats: conflict-free scalar writes) and
+// writes each (v, b) row of 16 a' x 2 t as one 128-byte run.  Same FP64
+// accumulation as the other steps.  Needs d = 2, da % 16 == 0, db % 64 == 0.
+constexpr int kKmTa = 16, kKmTb = 64, kKmRow = kKmTa * 2 + 1;
+
+template <int WL, int WR>
+__global__ void __launch_bounds__(256) wstep_left_kmajor(const float* __restrict__ t1, float* __restrict__ t2,
+                                                         const float* __restrict__ w, int64_t w0, int64_t w1,
+                                                         int64_t w2, int64_t w3, int da, int db) {
+  constexpr int D = 2;
+  __shared__ float sw[WL * WR * D * D];
+  __shared__ float tile[WR * kKmTb * kKmRow];
+  for (int i = threadIdx.x; i < WL * WR * D * D; i += blockDim.x) {
+    const int s = i % D, t = (i / D) % D, v = (i / (D * D)) % WR, u = i / (D * D * WR);
+    sw[i] = w[u * w0 + v * w1 + t * w2 + s * w3];
+  }
+  __syncthreads();
+  const int a0 = blockIdx.y * kKmTa, b0 = blockIdx.x * kKmTb;
+  const int al = threadIdx.x / (kKmTb / 4), bq = threadIdx.x % (kKmTb / 4);
+  const int64_t a = a0 + al;
+  const int b = b0 + bq * 4;
+  f32x4w_t x[WL][D];
+#pragma unroll
+  for (int u = 0; u < WL; ++u)
+#pragma unroll
+    for (int s = 0; s < D; ++s) x[u][s] = *reinterpret_cast<const f32x4w_t*>(t1 + ((a * WL + u) * D + s) * db + b);
+#pragma unroll
+  for (int t = 0; t < D; ++t)
+#pragma unroll
+    for (int v = 0; v < WR; ++v) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < WL; ++u)
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          const double c = sw[((u * WR + v) * D + t) * D + s];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] += c * (double)x[u][s][e];
+        }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tile[(v * kKmTb + bq * 4 + e) * kKmRow + al * D + t] = (float)acc[e];
+    }
+  __syncthreads();
+  // (v, b) rows of 32 floats; eight threads per row, four floats each
+  for (int i = threadIdx.x; i < WR * kKmTb * 8; i += 256) {
+    const int row = i / 8, c4 = (i % 8) * 4;
+    const int v = row / kKmTb, bl = row % kKmTb;
+    const float* src = tile + row * kKmRow + c4;
+    const f32x4w_t o = {src[0], src[1], src[2], src[3]};
+    *reinterpret_cast<f32x4w_t*>(t2 + (((int64_t)v * db + b0 + bl) * da + a0) * D + c4) = o;
+  }
+}
+
+typedef void (*WstepKmFn)(const float*, float*, const float*, int64_t, int64_t, int64_t, int64_t, int, int);
+template <int WL>
+static WstepKmFn km_pick(int wr) {
+  switch (wr) {
+    case 1: return wstep_left_kmajor<WL, 1>;
+    case 2: return wstep_left_kmajor<WL, 2>;
+    case 3: return wstep_left_kmajor<WL, 3>;
+    case 4: return wstep_left_kmajor<WL, 4>;
+    case 5: return wstep_left_kmajor<WL, 5>;
+    default: return nullptr;
+  }
+}
+static WstepKmFn wstep_left_km_fn(int wl, int wr, int d, int64_t da, int64_t db, const void* t1, const void* t2) {
+  if (d != 2 || da % kKmTa || db % kKmTb || reinterpret_cast<uintptr_t>(t1) % 16 || reinterpret_cast<uintptr_t>(t2) % 16)
+    return nullptr;
+  switch (wl) {
+    case 1: return km_pick<1>(wr);
+    case 2: return km_pick<2>(wr);
+    case 3: return km_pick<3>(wr);
+    case 4: return km_pick<4>(wr);
+    case 5: return km_pick<5>(wr);
+    default: return nullptr;
+  }
+}
+
 typedef void (*WstepLeftFn)(const float*, float*, const float*, int64_t, int64_t, int64_t, int64_t, int);
 typedef void (*WstepRightFn)(const float*, float*, const float*, int64_t, int64_t, int64_t, int64_t, int, int);
 
@@ -613,6 +695,23 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
     TN_TRY(plan_gemm(cur, psi[k], 1, a1, b1, T1, g));
     TN_TRY(launch_gemm(g, prec, s));
     const tn_tensor& W = mpo[k];
+    const int32_t a3[2] = {0, 1}, b3[2] = {0, 1};
+    if (WstepKmFn f = wstep_left_km_fn((int)wl, (int)wr, (int)d, da, db, t1, t2)) {
+      // T2 in memory order [v, b, a', t]: the view keeps the axis order (a', t, v, b)
+      hipLaunchKernelGGL(f, dim3((unsigned)(db / kKmTb), (unsigned)(da / kKmTa)), dim3(256), 0, s, t1, t2,
+                         static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
+                         (int)db);
+      TN_TRY(hip_check(hipGetLastError(), "wstep left"));
+      tn_tensor T2k = T2;
+      T2k.stride[0] = d;
+      T2k.stride[1] = 1;
+      T2k.stride[2] = db * da * d;
+      T2k.stride[3] = da * d;
+      TN_TRY(plan_gemm(psi[k], T2k, 2, a3, b3, nxt, g));
+      TN_TRY(launch_gemm(g, prec, s));
+      cur = nxt;
+      return TN_OK;
+    }
     if (WstepLeftFn f = wstep_left_fn((int)wl, (int)wr, (int)d, db, t1, t2))
       hipLaunchKernelGGL(f, dim3((unsigned)((db / 4 + 255) / 256), (unsigned)da), dim3(256), 0, s, t1, t2,
                          static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)db);
@@ -621,7 +720,6 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
                          static_cast<const float*>(W.data), W.stride[0], W.stride[1], W.stride[2], W.stride[3], (int)da,
                          (int)db, (int)wl, (int)wr, (int)d);
     TN_TRY(hip_check(hipGetLastError(), "wstep left"));
-    const int32_t a3[2] = {0, 1}, b3[2] = {0, 1};
     TN_TRY(plan_gemm(psi[k], T2, 2, a3, b3, nxt, g));
     TN_TRY(launch_gemm(g, prec, s));
     cur = nxt;
