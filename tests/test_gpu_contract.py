@@ -430,6 +430,13 @@ def test_reduction_layout_paths():
     out = tn.trace_edge(gpu(t), 0, 2)
     _rounded_close(host(out), oracle.trace_edge(t.astype(np.float64), 0, 2),
                    oracle.trace_edge(np.abs(t).astype(np.float64), 0, 2), "trace outer axes")
+    # few output quads: four threads share each quad, each over every fourth k
+    # (32 diagonal terms; 20 terms, not a multiple of four; a ragged last workgroup)
+    for shape in ((32, 32, 4096), (20, 20, 2048), (16, 16, 1028)):
+        t = f32(rng.standard_normal(shape))
+        out = tn.trace_edge(gpu(t), 0, 1)
+        _rounded_close(host(out), oracle.trace_edge(t.astype(np.float64), 0, 1),
+                       oracle.trace_edge(np.abs(t).astype(np.float64), 0, 1), f"trace k-split {shape}")
     for na, nb in ((37, 1024), (5, 1023), (3, 4)):
         a = f32(rng.standard_normal(na))
         b = f32(rng.standard_normal(nb))
