@@ -228,7 +228,10 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
  * diag(R) >= 0; Q replaces A_k, R is absorbed into A_{k+1}; the final 1x1 R
  * is the state's norm, written as its logarithm to *lognorm (DEVICE) and
  * divided out.  sites: TN_F64, contiguous, modified in place.  Requires
- * D_{k+1} <= d * D_k.
+ * D_{k+1} <= d * D_k.  Each site's Q is formed on the library-owned side
+ * stream (one per device, default priority) while the next site is
+ * factorised; the call joins it back into `stream` before it returns, so all
+ * of its work stays ordered on `stream`.
  * ------------------------------------------------------------------- */
 int32_t tn_mps_left_canonicalize_workspace(int32_t n_sites, const tn_tensor* sites, size_t* bytes);
 int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* lognorm,

@@ -66,6 +66,10 @@ int grouped_variant(const Gemm2D& p);
 int32_t launch_gemm_grouped(const Gemm2D* dev_probs, const int32_t* dev_tile_start, int32_t n_probs,
                             int32_t total_tiles, int32_t prec, int cfg, int variant, hipStream_t st);
 int grouped_tile_m(int cfg);
+// the library's second stream on the current device (created on first use,
+// default priority, never destroyed): work forked from and joined back into
+// the caller's stream by events
+int32_t side_stream(hipStream_t& out);
 // grouped tile configuration pinned by tn_tune_force_grouped_config, or -1
 int forced_grouped_cfg();
 int grouped_tile_n(int cfg);

@@ -506,7 +506,7 @@ static EnvLayout env_layout(int32_t n, const std::vector<int64_t>& dims, const s
 
 // A second stream per device (default priority) on which the right sweep
 // runs beside the left one; created on first use and kept for the process.
-static int32_t side_stream(hipStream_t& out) {
+int32_t side_stream(hipStream_t& out) {
   static std::mutex mu;
   static std::vector<hipStream_t> streams;
   int dev = 0;

@@ -160,13 +160,16 @@ __device__ inline void qr_block_sum(double (&v)[NV], double (*red)[kQrWaves * 64
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane < P) red[buf][wave * P + lane] = r;
   __syncthreads();
+  // lane i < NV of every wavefront adds the wavefronts' partial sums of value
+  // i (in wavefront order), and every lane takes value i from lane i: eight
+  // LDS reads per lane instead of eight per value
+  double t = 0.0;
+  if (lane < NV) {
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double t = 0.0;
-#pragma unroll
-    for (int wv = 0; wv < kQrWaves; ++wv) t += red[buf][wv * P + i];
-    v[i] = t;
+    for (int wv = 0; wv < kQrWaves; ++wv) t += red[buf][wv * P + lane];
   }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = __shfl(t, i, 64);
   buf ^= 1;
 }
 
@@ -426,14 +429,19 @@ __global__ void eye_kernel(double* qc, int m, int n) {
 }
 
 // site[i, s, b] = Q[(i d + s), b] * sign(R[b, b]);  R_next[r, c] = sign(R[r, r]) * R[r, c] (upper)
-__global__ void finalize_kernel(const double* __restrict__ xc, const double* __restrict__ qc, double* site,
-                                double* rnext, int m, int n) {
+// Q with column signs so that diag(R) >= 0, written over the site
+__global__ void finalize_q_kernel(const double* __restrict__ xc, const double* __restrict__ qc, double* site, int m,
+                                  int n) {
   const int64_t total = (int64_t)m * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t row = e / n, b = e - row * n;   // row-major site index (row = i*d + s)
     double sg = xc[b * m + b] < 0.0 ? -1.0 : 1.0;
     site[e] = qc[b * m + row] * sg;
   }
+}
+
+// R with row signs (diag(R) >= 0), row-major, for the next site's absorb
+__global__ void finalize_r_kernel(const double* __restrict__ xc, double* rnext, int m, int n) {
   const int64_t tr = (int64_t)n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tr; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t r = e / n, c = e - r * n;
@@ -455,8 +463,10 @@ static unsigned blocks_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 16384));
 }
 
+// X, Q and T come in two sets, used by alternate sites: a site's Q is formed
+// on the side stream while the next site is factorised
 struct QrLayout {
-  size_t x, q, r, tau, tf, total;
+  size_t x[2], q[2], r, tau, tf[2], total;
 };
 
 static int32_t qr_check(int32_t n, const tn_tensor* sites, QrLayout& L) {
@@ -479,12 +489,20 @@ static int32_t qr_check(int32_t n, const tn_tensor* sites, QrLayout& L) {
     prev = t.shape[2];
   }
   if (sites[0].shape[0] != 1 || prev != 1) return fail(TN_ERR_SHAPE_MISMATCH, "boundary bonds must be 1");
-  L.x = 0;
-  L.q = al256(mx * 8);
-  L.r = L.q + al256(mx * 8);
-  L.tau = L.r + al256(std::max<int64_t>(mr, 1) * 8);
-  L.tf = L.tau + al256(4096 * 8);
-  L.total = L.tf + al256((4096 / kQrNb) * kQrNb * kQrNb * 8);
+  size_t o = 0;
+  for (int h = 0; h < 2; ++h) {
+    L.x[h] = o;
+    o += al256(mx * 8);
+    L.q[h] = o;
+    o += al256(mx * 8);
+    L.tf[h] = o;
+    o += al256((4096 / kQrNb) * kQrNb * kQrNb * 8);
+  }
+  L.r = o;
+  o += al256(std::max<int64_t>(mr, 1) * 8);
+  L.tau = o;
+  o += al256(4096 * 8);
+  L.total = o;
   int64_t maxn = 1;
   for (int k = 0; k < n; ++k) maxn = std::max(maxn, sites[k].shape[2]);
   if (maxn > 4096) return fail(TN_ERR_UNSUPPORTED, "bond dimension above 4096");
@@ -513,19 +531,42 @@ int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* logn
   if (!workspace || ws_bytes < L.total) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", L.total);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  double* xc = reinterpret_cast<double*>(ws + L.x);
-  double* qc = reinterpret_cast<double*>(ws + L.q);
   double* r = reinterpret_cast<double*>(ws + L.r);
   double* tau = reinterpret_cast<double*>(ws + L.tau);
-  double* tf = reinterpret_cast<double*>(ws + L.tf);
+  // Site k's factorisation and R run on the caller's stream; its Q (the
+  // reflectors applied to [I; 0]) and the write-back run on the side stream,
+  // overlapping site k+1's factorisation, whose one-workgroup panels leave
+  // most of the chip idle.  Site k+2 reuses site k's X, Q and T only after
+  // that Q is done (event per set); the call ends joined on the caller's stream.
+  hipStream_t side = st;
+  TN_TRY(side_stream(side));
+  hipEvent_t ev_fact = nullptr, ev_q[2] = {nullptr, nullptr};
+  struct EventGuard {
+    hipEvent_t* e[3];
+    ~EventGuard() {
+      for (hipEvent_t* p : e)
+        if (*p) hipEventDestroy(*p);
+    }
+  } guard{{&ev_fact, &ev_q[0], &ev_q[1]}};
+  for (hipEvent_t* e : guard.e)
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return fail(TN_ERR_DEVICE, "create event failed");
+  hipEventRecord(ev_q[0], st);
+  hipEventRecord(ev_q[1], st);
   hipLaunchKernelGGL(one_kernel, dim3(1), dim3(64), 0, st, r);
-  for (int k = 0; k < n_sites; ++k) {
+  int32_t rc = TN_OK;
+  for (int k = 0; k < n_sites && rc == TN_OK; ++k) {
+    const int h = k & 1;
+    double* xc = reinterpret_cast<double*>(ws + L.x[h]);
+    double* qc = reinterpret_cast<double*>(ws + L.q[h]);
+    double* tf = reinterpret_cast<double*>(ws + L.tf[h]);
     const int dk = (int)sites[k].shape[0], d = (int)sites[k].shape[1], dn = (int)sites[k].shape[2];
     const int m = dk * d, n = dn;
     double* a = static_cast<double*>(sites[k].data);
+    hipStreamWaitEvent(st, ev_q[h], 0);   // site k-2's Q no longer reads this set
     dim3 g((unsigned)((d * dn + 63) / 64), (unsigned)((dk + 63) / 64));
     hipLaunchKernelGGL(absorb_kernel, g, dim3(256), 0, st, r, a, xc, dk, d, dn);
-    if (m <= kQrThreads * kQrRows) {
+    const bool blocked = m <= kQrThreads * kQrRows;
+    if (blocked) {
       for (int j0 = 0; j0 < n; j0 += kQrNb) {
         const int nb = std::min(kQrNb, n - j0);
         hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(kQrThreads), 0, st, xc, tau, tf, m, j0, nb);
@@ -534,24 +575,39 @@ int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* logn
           hipLaunchKernelGGL(qr_apply_kernel, dim3((unsigned)((rest + kQrCb - 1) / kQrCb)), dim3(kQrThreads), 0, st, xc,
                              tf, xc, m, j0, nb, j0 + nb, rest, 1);
       }
-      hipLaunchKernelGGL(eye_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, st, qc, m, n);
-      for (int j0 = (n - 1) / kQrNb * kQrNb; j0 >= 0; j0 -= kQrNb) {
-        const int nb = std::min(kQrNb, n - j0);
-        hipLaunchKernelGGL(qr_apply_kernel, dim3((unsigned)((n - j0 + kQrCb - 1) / kQrCb)), dim3(kQrThreads), 0, st, xc,
-                           tf, qc, m, j0, nb, j0, n - j0, 0);
-      }
     } else {
       for (int j = 0; j < n; ++j) {
         hipLaunchKernelGGL(reflector_kernel, dim3(1), dim3(256), 0, st, xc, tau, m, j);
         if (j + 1 < n) hipLaunchKernelGGL(reflect_cols_kernel, dim3(n - j - 1), dim3(256), 0, st, xc, tau, xc, m, j, j + 1);
       }
-      hipLaunchKernelGGL(eye_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, st, qc, m, n);
-      for (int j = n - 1; j >= 0; --j)
-        hipLaunchKernelGGL(reflect_cols_kernel, dim3(n - j), dim3(256), 0, st, xc, tau, qc, m, j, j);
     }
-    hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, st, xc, qc, a, r, m, n);
-    TN_TRY(hip_check(hipGetLastError(), "canonicalize"));
+    hipLaunchKernelGGL(finalize_r_kernel, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, st, xc, r, m, n);
+    // Q: on the side stream for the blocked path; the column path's Q needs
+    // tau, which the next site overwrites, so it stays on the caller's stream
+    hipStream_t qs = blocked ? side : st;
+    if (blocked) {
+      hipEventRecord(ev_fact, st);
+      hipStreamWaitEvent(side, ev_fact, 0);
+    }
+    hipLaunchKernelGGL(eye_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, qs, qc, m, n);
+    if (blocked) {
+      for (int j0 = (n - 1) / kQrNb * kQrNb; j0 >= 0; j0 -= kQrNb) {
+        const int nb = std::min(kQrNb, n - j0);
+        hipLaunchKernelGGL(qr_apply_kernel, dim3((unsigned)((n - j0 + kQrCb - 1) / kQrCb)), dim3(kQrThreads), 0, qs, xc,
+                           tf, qc, m, j0, nb, j0, n - j0, 0);
+      }
+    } else {
+      for (int j = n - 1; j >= 0; --j)
+        hipLaunchKernelGGL(reflect_cols_kernel, dim3(n - j), dim3(256), 0, qs, xc, tau, qc, m, j, j);
+    }
+    hipLaunchKernelGGL(finalize_q_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, qs, xc, qc, a, m, n);
+    hipEventRecord(ev_q[h], qs);
+    rc = hip_check(hipGetLastError(), "canonicalize");
   }
+  // join: every Q written back before the call's later work on the caller's stream
+  hipStreamWaitEvent(st, ev_q[0], 0);
+  hipStreamWaitEvent(st, ev_q[1], 0);
+  TN_TRY(rc);
   hipLaunchKernelGGL(lognorm_kernel, dim3(1), dim3(64), 0, st, r, lognorm);
   return hip_check(hipGetLastError(), "lognorm");
 }
