@@ -60,7 +60,7 @@ __device__ inline double contig_sum(const ReduceDesc& d, const float* x, const f
   int64_t k = k0;
   if (vec) {
     const int64_t n4 = (k1 - k0) / 4;
-    for (int64_t i = lane; i < n4; i += nlanes) {
+    auto quad = [&](int64_t i, double& a4) {
       f4_t xv = *reinterpret_cast<const f4_t*>(x + k0 + 4 * i);
       f4_t yv = y ? *reinterpret_cast<const f4_t*>(y + k0 + 4 * i) : f4_t{1.f, 1.f, 1.f, 1.f};
 #pragma unroll
@@ -70,9 +70,19 @@ __device__ inline double contig_sum(const ReduceDesc& d, const float* x, const f
           a = bf16_rne(a);
           b = bf16_rne(b);
         }
-        acc += (double)a * (double)b;
+        a4 += (double)a * (double)b;
       }
+    };
+    // four independent partial sums (added in a fixed order at the end), so
+    // four 16-byte loads per lane are in flight instead of one FP64 add chain
+    double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = lane;
+    for (; i + 3 * nlanes < n4; i += 4 * nlanes) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) quad(i + u * nlanes, acc4[u]);
     }
+    for (; i < n4; i += nlanes) quad(i, acc4[0]);
+    acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
     k = k0 + 4 * n4;
   }
   for (int64_t i = k + lane; i < k1; i += nlanes) {
@@ -328,13 +338,13 @@ int32_t launch_reduce(ReduceDesc& d, void* scratch, size_t scratch_bytes, hipStr
     blocks = (d.R + 255) / 256;
   else if (d.mode == 3)
     blocks = (d.R / 4 + 255) / 256;
-  // few workgroups of outputs and a k range worth splitting: four threads per output quad
-  const bool ksplit = d.mode == 3 && blocks < 1024 && d.K >= 16;
-  if (ksplit) blocks = (d.R / 4 + 63) / 64;
   else if (d.mode == 1)
     blocks = (d.R + 3) / 4;
   else
     blocks = d.R;
+  // few workgroups of outputs and a k range worth splitting: four threads per output quad
+  const bool ksplit = d.mode == 3 && blocks < 1024 && d.K >= 16;
+  if (ksplit) blocks = (d.R / 4 + 63) / 64;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   if (d.mode == 3 && ksplit)
