@@ -242,6 +242,23 @@ struct OperandLoader {
         if (((rowok >> v) & 1u) && k < K) x = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k));
         st[v] = x;
       }
+    } else if ((mode == LOAD_MNSCALAR || mode == LOAD_GENERIC) && gk.n == 1) {
+      // one contracted axis: one offset per micro-block, its four k at
+      // multiples of the stride (the scalar gathers of both forms below)
+      const int64_t sk = gk.s[KIDX][0];
+#pragma unroll
+      for (int v = 0; v < VK; ++v) {
+        int idx = tid + v * NT;
+        int k = k0 + (mode == LOAD_MNSCALAR ? idx / R : idx % KQ) * 4;
+        f32x4_t x = {0.f, 0.f, 0.f, 0.f};
+        if ((rowok >> v) & 1u) {
+          const float* p = base + rowoff[v] + (int64_t)k * sk;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (k + j < K) x[j] = p[j * sk];
+        }
+        st[v] = x;
+      }
     } else if (mode == LOAD_MNSCALAR) {
       // lanes run along the unit-stride rows: each load instruction reads
       // 64 consecutive floats of one k
