@@ -113,9 +113,10 @@ bool is_contiguous(const tn_tensor& t) {
 // total work: the estimate is, in units of one wave's 32 x 32 block times one
 // k, the larger of the longest wave's work and the total padded work spread
 // over the 1024 SIMDs, divided by a per-wave efficiency of the tile shape.
-// The efficiencies follow measurement on a batch of 32 chains with odd bond
-// dimensions (run-time gathers; N up to 256, chi up to 512): the k-sliced
-// 64 x 64 tile throughout was fastest, the 128 x 128 tile throughout slowest.
+// The efficiencies follow per-launch measurement on a batch of 32 chains
+// with odd bond dimensions (run-time gathers; N up to 256, chi up to 512):
+// the 128 x 128 tile was 10-25 % faster on the full steps, the k-sliced
+// 64 x 64 tile about twice as fast on the last steps, where few tiles run.
 //   0: 128 x 128 (four 64 x 64 waves)   1: 64 x 64 (four 32 x 32 waves)
 //   3: 64 x 64 in two k-slices (eight waves, each over half of K)
 //   2: 32 x 32 when every problem of the step fits one such tile
@@ -131,7 +132,7 @@ int step_cfg(const std::vector<Gemm2D>& v) {
     double per_wave;  // blocks x k per wave, per k of the problem
     double eff;
   };
-  static const Cand cands[] = {{0, 128, 4.0, 0.6}, {1, 64, 1.0, 0.8}, {3, 64, 0.5, 1.0}};
+  static const Cand cands[] = {{0, 128, 4.0, 1.2}, {1, 64, 1.0, 0.9}, {3, 64, 0.5, 1.0}};
   int best = 0;
   double best_t = 1e300;
   for (const Cand& c : cands) {
