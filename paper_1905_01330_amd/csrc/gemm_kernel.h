@@ -246,6 +246,7 @@ struct OperandLoader {
       // one contracted axis: one offset per micro-block, its four k at
       // multiples of the stride (the scalar gathers of both forms below)
       const int64_t sk = gk.s[KIDX][0];
+      const bool full = k0 + BK <= K;   // every k of the stage in range: no per-element checks
 #pragma unroll
       for (int v = 0; v < VK; ++v) {
         int idx = tid + v * NT;
@@ -253,9 +254,14 @@ struct OperandLoader {
         f32x4_t x = {0.f, 0.f, 0.f, 0.f};
         if ((rowok >> v) & 1u) {
           const float* p = base + rowoff[v] + (int64_t)k * sk;
+          if (full) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (k + j < K) x[j] = p[j * sk];
+            for (int j = 0; j < 4; ++j) x[j] = p[j * sk];
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (k + j < K) x[j] = p[j * sk];
+          }
         }
         st[v] = x;
       }
