@@ -36,17 +36,21 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
-// Xc[b * m + (i * d + s)] = sum_l R[i, l] A[l, s, b]     (R: dk x dk row-major)
+// Xc[b * m + (i * d + s)] = sum_l R[i, l] A[l, s, b]     (R: dk x dk row-major,
+// upper triangular: the sum starts at l = i, so a row block skips the l
+// blocks below it).  The 64 x 64 result tile goes through LDS so that the
+// column-major stores run along i.
 __global__ void __launch_bounds__(256) absorb_kernel(const double* __restrict__ r, const double* __restrict__ a,
                                                      double* __restrict__ xc, int dk, int d, int dn) {
   __shared__ double sr[64][17];
   __shared__ double sa[16][65];
+  __shared__ double so[64][65];
   const int m = dk * d;
   const int p = d * dn;            // columns of A viewed (dk, d*dn)
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[4][4] = {};
-  for (int l0 = 0; l0 < dk; l0 += 16) {
+  for (int l0 = i0; l0 < dk; l0 += 16) {
     for (int e = threadIdx.x; e < 64 * 16; e += 256) {
       int ii = e / 16, ll = e % 16;
       sr[ii][ll] = (i0 + ii < dk && l0 + ll < dk) ? r[(int64_t)(i0 + ii) * dk + l0 + ll] : 0.0;
@@ -62,15 +66,20 @@ __global__ void __launch_bounds__(256) absorb_kernel(const double* __restrict__ 
         for (int v = 0; v < 4; ++v) acc[u][v] = fma(sr[ty * 4 + u][ll], sa[ll][tx * 4 + v], acc[u][v]);
     __syncthreads();
   }
+#pragma unroll
   for (int u = 0; u < 4; ++u)
-    for (int v = 0; v < 4; ++v) {
-      int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-      if (i < dk && j < p) {
-        int s = j / dn, b = j - s * dn;
-        xc[(int64_t)b * m + i * d + s] = acc[u][v];
-      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) so[ty * 4 + u][tx * 4 + v] = acc[u][v];
+  __syncthreads();
+  // consecutive threads take consecutive i of one column j = (s, b)
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int jl = e / 64, il = e % 64;
+    const int i = i0 + il, j = j0 + jl;
+    if (i < dk && j < p) {
+      const int s = j / dn, b = j - s * dn;
+      xc[(int64_t)b * m + i * d + s] = so[il][jl];
     }
-  (void)m;
+  }
 }
 
 // reflector for column j of the column-major m x n matrix X (LAPACK larfg convention)
