@@ -15,7 +15,11 @@ stream it runs on, over replays of a HIP graph of that contraction alone
 (`--mode tensordot` issues the same contraction eagerly, for profiling).  `cpu_baseline` times the FP64 oracle
 on a bounded sample of bulk sites of the same sweep.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode sweep|tensordot]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode sweep|tensordot|rows|batched|canonicalize]
+
+`--mode batched` and `--mode canonicalize` run one row alone (the uneven batch of
+the first 32 chains in FP32; the FP64 canonicalisation of the chi = 1024 chain),
+for kernel-trace profiles.
 """
 from __future__ import annotations
 
@@ -40,7 +44,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows"], default="sweep")
+    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "batched", "canonicalize"], default="sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     return ap.parse_args()
 
@@ -345,7 +349,7 @@ def rows(torch, tn, inputs):
                     cfl, c, "one bulk left step (FP64)", {"precision": "split_bf16"}))
     del sw
 
-    # a12: uneven batch, the first 48 chains of the 512-chain workload
+    # a12: uneven batch, the first 32 chains of the 512-chain workload
     shapes = inputs.uneven_chain_shapes()[:32]
     chains, bfl = [], 0.0
     for i, (nn, chi) in enumerate(shapes):
@@ -449,6 +453,32 @@ def main():
             p = f" ({r['precision']})" if "precision" in r else ""
             print(f"| {r['row']}{p} | {r['workload']} | {r['ms']:.3f} | {f['achieved']:.3g} {f['unit']} | "
                   f"{f['bound']} {f['peak']:g} | {f['frac']:.4f} | {o['value']:.3g} {o['unit']} ({o['sample']}) |")
+        return
+    if a.mode == "batched":
+        dev = torch.device("cuda:0")
+        chains = []
+        for i, (nn, chi) in enumerate(inputs.uneven_chain_shapes()[:32]):
+            p, q = inputs.uneven_chain(i, nn, chi)
+            chains.append(([torch.tensor(x, dtype=torch.float32, device=dev) for x in p],
+                           [torch.tensor(x, dtype=torch.float32, device=dev) for x in q]))
+        bi = tn.BatchedInner(chains, "fp32")
+        ms = time_loop(torch, bi.run, a.steps, a.warmup)
+        print(json.dumps({"mode": "batched", "chains": 32, "precision": "fp32", "ms_per_call": round(ms, 4)}))
+        return
+    if a.mode == "canonicalize":
+        dev = torch.device("cuda:0")
+        raw = [torch.tensor(x, device=dev) for x in inputs.random_mps(N_SITES, 2, CHI, SEED)]
+        times = []
+        for it in range(a.warmup + a.steps):
+            sites = [x.clone() for x in raw]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tn.mps_left_canonicalize(sites)
+            torch.cuda.synchronize()
+            if it >= a.warmup:
+                times.append(time.perf_counter() - t0)
+        print(json.dumps({"mode": "canonicalize", "n_sites": N_SITES, "chi": CHI,
+                          "ms_per_call": round(1e3 * sum(times) / max(len(times), 1), 3)}))
         return
     if a.mode == "tensordot":
         tn.tune_set_level(1)

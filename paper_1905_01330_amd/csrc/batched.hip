@@ -48,17 +48,21 @@ __device__ inline int slot_exponent(uint32_t bits) {
 // one workgroup per chain: sum_{a', a} E_L[a', a] E_R[a', a] at the middle
 // bond in FP64 (products of FP32 values are exact), times 2^(the exponents
 // applied on both sides), written as a mantissa in [0.5, 1) and a log scale
-__global__ void __launch_bounds__(256) batched_finish_kernel(const ChainRec* chains, int n_chains, double* out2) {
-  __shared__ double red[2][4];
+constexpr int kFinishThreads = 1024;
+
+__global__ void __launch_bounds__(kFinishThreads) batched_finish_kernel(const ChainRec* chains, int n_chains,
+                                                                        double* out2) {
+  constexpr int NW = kFinishThreads / 64;
+  __shared__ double red[2][NW];
   const int c = blockIdx.x;
   if (c >= n_chains) return;
   const ChainRec r = chains[c];
   const float* el = r.e[r.c & 1];
   const float* er = r.er[(r.n - r.c) & 1];
   double v = 0.0, s = 0.0;
-  for (int64_t i = threadIdx.x; i < r.cnt; i += 256) v += (double)el[i] * (double)er[i];
-  for (int i = threadIdx.x; i < r.c; i += 256) s += (double)slot_exponent(r.slots[i]);
-  for (int i = threadIdx.x; i < r.n - r.c; i += 256) s += (double)slot_exponent(r.rslots[i]);
+  for (int64_t i = threadIdx.x; i < r.cnt; i += kFinishThreads) v += (double)el[i] * (double)er[i];
+  for (int i = threadIdx.x; i < r.c; i += kFinishThreads) s += (double)slot_exponent(r.slots[i]);
+  for (int i = threadIdx.x; i < r.n - r.c; i += kFinishThreads) s += (double)slot_exponent(r.rslots[i]);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     v += __shfl_xor(v, o, 64);
@@ -70,8 +74,12 @@ __global__ void __launch_bounds__(256) batched_finish_kernel(const ChainRec* cha
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double total = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    const double ex = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    double total = 0.0, ex = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      total += red[0][w];
+      ex += red[1][w];
+    }
     int e2 = 0;
     const double m = frexp(total, &e2);
     out2[2 * c] = m;
@@ -401,7 +409,7 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   for (const Launch& L : Q.launches)
     TN_TRY(launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off, L.n_probs, L.tiles, prec, L.cfg, L.variant,
                                st));
-  hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(256), 0, st, d_chains, n_chains, out2);
+  hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(kFinishThreads), 0, st, d_chains, n_chains, out2);
   return hip_check(hipGetLastError(), "batched finish");
 }
 
