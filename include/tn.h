@@ -244,15 +244,23 @@ int32_t tn_mps_left_canonicalize(int32_t n_sites, tn_tensor* sites, double* logn
  * [0, 1], encoded by Phi(p) = (cos(pi p/2), sin(pi p/2)).
  * logits: TN_F32 [B, n_labels], f[b, l] = <W^l, Phi(x_b)>.
  * Forward keeps every left/right environment vector of each sample on chip
- * and stores one of every `ckpt_every` of them to ckpt (nullable; FP32,
- * layout documented by tn_mps_classifier_ckpt_shape) for the backward.
+ * and stores one of every `ckpt_every` of them to ckpt (nullable; an opaque
+ * buffer of the 4-byte words that tn_mps_classifier_ckpt_shape counts: per
+ * checkpoint the B vectors as FP32 high parts, B power-of-two exponents and
+ * the FP32 low parts, so a stored vector keeps about 48 significant bits)
+ * for the backward.  The running vectors handed from one chain launch to
+ * the next keep the same two-part form.
  * Backward: dlogits [B, n_labels] -> dsites (same shapes as sites); it
  * recomputes the vectors between checkpoints (ckpt is required there).
  * prec: FP32 or SPLIT_BF16; it applies to the label-site and weight-gradient
- * contractions, the chain steps themselves run on FP32 matrix cores.
+ * contractions.  The chain steps themselves (one site after another for
+ * every sample) run on the FP64 matrix cores with FP64 running vectors,
+ * stored as FP32 between kernel runs: FP32 chain steps compounded over 784
+ * sites to about 3e-5 relative on the scores.
  * Requirements: 1 <= label_site <= n_sites - 2, chi <= 256, every site
  * contiguous, 1 <= ckpt_every <= 64.
  * ------------------------------------------------------------------- */
+/* n_floats: 4-byte words of the checkpoint buffer for this geometry. */
 int32_t tn_mps_classifier_ckpt_shape(int32_t n_sites, int32_t label_site, int32_t batch,
                                      int32_t chi, int32_t ckpt_every, int64_t* n_floats);
 int32_t tn_mps_classifier_workspace(int32_t n_sites, int32_t label_site, int32_t n_labels,
@@ -276,13 +284,32 @@ int32_t tn_softmax_xent(const tn_tensor* logits, const int64_t* labels, int32_t 
                         tn_tensor* dlogits, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
- * Tile autotuner for the contraction GEMM.  level 0: heuristic tiles only;
- * 1: time the candidate tiles once per new (shape, layout, precision)
- * signature on first use and cache the fastest.  The cache is process-wide
- * and mutex-guarded.  tn_tune_lookup reports the tile id chosen for the
- * last contraction on this thread (for logging).
+ * Tile autotuner for the contraction GEMM.
+ * level 0: heuristic tiles only;
+ *       1: on the first contraction of each new (shape, layout, precision)
+ *          signature, time every candidate tile 3 times and keep the fastest;
+ *       2: the same with 10 timed launches per candidate (less noise).
+ * Tile choices are cached per process; the cache is mutex-guarded, so
+ * concurrent calls from several threads are safe.  Timing is skipped while
+ * the stream is being captured into a graph (the heuristic is used then).
+ *
+ * tn_tune(cache_path, level): sets the level and, when cache_path is not
+ * NULL, persists the choices in that text file: entries already in it are
+ * loaded now (lines "M N K batch amode bmode cmode prec groups -> cfg",
+ * malformed lines are skipped) and every choice made later is appended.
+ * NULL keeps the choices in memory only.  Changing the level clears the
+ * in-memory choices (the file is reloaded).  The environment variables
+ * TN_TUNE=off|quick|full and TN_TUNE_CACHE=<path> give the starting state
+ * when the library loads.  Errors: TN_ERR_INVALID_ARGUMENT for a level
+ * outside 0..2, TN_ERR_DEVICE if the file cannot be opened for appending.
  * ------------------------------------------------------------------- */
+int32_t tn_tune(const char* cache_path, int32_t level);
+/* The same as tn_tune(NULL, level) without touching the cache file setting
+ * (level 0 or 1). */
 int32_t tn_tune_set_level(int32_t level);
+/* Tile id chosen for the last contraction GEMM on this thread (-1: none
+ * yet; calls served by the reduction or small-extent paths do not change
+ * it).  For logging and tests. */
 int32_t tn_tune_last_choice(void);
 /* Pin one tile configuration (0 .. tn_tune_num_configs()-1) for every
  * subsequent contraction GEMM in the process; -1 restores automatic choice.

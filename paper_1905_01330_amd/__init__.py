@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     softmax_xent,
     tensordot,
     trace_edge,
+    tune,
     tune_force_config,
     tune_force_grouped_config,
     tune_last_choice,

@@ -72,6 +72,7 @@ _PROTOS = {
     "tn_mps_classifier_forward": (I32, [I32, I32, I32, TP, TP, TP, P, I32, P, SZ, I32, P]),
     "tn_mps_classifier_backward": (I32, [I32, I32, I32, TP, TP, P, I32, TP, TP, P, SZ, I32, P]),
     "tn_softmax_xent": (I32, [TP, P, I32, P, TP, P, SZ, P]),
+    "tn_tune": (I32, [C.c_char_p, I32]),
     "tn_tune_set_level": (I32, [I32]),
     "tn_tune_last_choice": (I32, []),
     "tn_tune_force_config": (I32, [I32]),

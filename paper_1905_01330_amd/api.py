@@ -254,6 +254,13 @@ def mps_left_canonicalize(sites):
     return lognorm
 
 
+def tune(cache_path=None, level: int = 1):
+    """Tile autotuner level (0 heuristic, 1 quick, 2 full) and, optionally, a
+    text file that persists the tile choices across processes."""
+    path = None if cache_path is None else str(cache_path).encode()
+    L.check(L.lib().tn_tune(path, int(level)))
+
+
 def tune_set_level(level: int):
     L.check(L.lib().tn_tune_set_level(int(level)))
 

@@ -1,9 +1,12 @@
 """Build the gfx950 shared library libtn.so in-tree with hipcc.
 
-    python -m paper_1905_01330_amd.build [--jobs N]
+    python -m paper_1905_01330_amd.build [--jobs N] [--incremental]
 
 Every HIP/C++ source under csrc/ is compiled for gfx950 (packed FP32
 instructions disabled) and linked into paper_1905_01330_amd/libtn.so.
+--incremental recompiles only the sources whose object is older than the
+source or than any header under csrc/ or include/ (the default recompiles
+everything).
 """
 from __future__ import annotations
 
@@ -44,12 +47,26 @@ def _compile(src):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(src, newest_header):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return os.path.getmtime(src) > t or newest_header > t
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    todo = srcs
+    if incremental:
+        hdrs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
+        newest = max([os.path.getmtime(h) for h in hdrs] or [0.0])
+        todo = [s for s in srcs if _stale(s, newest)]
+    jobs = jobs or min(max(len(todo), 1), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,13 +74,14 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")
     os.replace(tmp, LIB)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources")
+        print(f"built {LIB} from {len(srcs)} sources ({len(todo)} compiled)")
     return LIB
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args()
-    build(a.jobs, verbose=True)
+    build(a.jobs, verbose=True, incremental=a.incremental)
     sys.exit(0)

@@ -43,11 +43,20 @@ struct ChainArgs {
   float* v_out;           // vector block (final vectors), may be NULL
   float* store;           // step inputs, may be NULL: step st's vectors at store + st * B * CHI,
   int64_t store_exp;      // its exponents at store + store_exp + st * B
+  int lo;                 // v_in and v_out carry their low parts (see vblock_floats)
 };
 
 // A "vector block" holds B vectors of length CHI (zero beyond their bond
-// dimension) followed by B exponents stored as floats: value = v * 2^e.
-__host__ __device__ inline int64_t vblock_floats(int B, int chi) { return (int64_t)B * chi + B; }
+// dimension), then B exponents stored as floats, then the low parts of the
+// B vectors: value = (hi + lo) * 2^e with hi = fl32(v), lo = fl32(v - hi).
+// The running vectors handed from one chain launch to the next (and the
+// checkpoints) keep the low parts, so the FP64 chain loses about 2^-48, not
+// 2^-24, at every hand-off: random transfer matrices amplify a rounding of
+// the running vector many times over by the end of the chain.  Blocks that
+// only feed FP32 GEMM operands (adjoints, recomputed segment vectors) do
+// not use the low parts.
+__host__ __device__ inline int64_t vblock_floats(int B, int chi) { return 2 * (int64_t)B * chi + B; }
+__host__ __device__ inline int64_t vblock_lo(int B, int chi) { return (int64_t)B * chi + B; }
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
@@ -235,19 +244,26 @@ __device__ __forceinline__ void chain_step(const ChainArgs& a, ChainSmem<CHI>& s
   // a stored block holds this site's output (the next site's input), normalised
   float* dst = nullptr;     // vectors of the block to write
   float* dste = nullptr;    // its exponents
+  float* dstl = nullptr;    // its low parts (running-vector hand-off only)
   if (a.store && st + 1 < a.n_steps) {
     dst = a.store + (int64_t)(st + 1) * a.B * CHI;
     dste = a.store + a.store_exp + (int64_t)(st + 1) * a.B;
   } else if (a.v_out && st + 1 == a.n_steps) {
     dst = a.v_out;
     dste = a.v_out + (int64_t)a.B * CHI;
+    if (a.lo) dstl = a.v_out + vblock_lo(a.B, CHI);
   }
   if (dst) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int rr = r * 4 + g, b = b0 + rr;
       const int er = row_exp(rr);
-      if (b < a.B) dst[(int64_t)b * CHI + col] = (float)ldexp(outv[r], -er);
+      if (b < a.B) {
+        const double x = ldexp(outv[r], -er);
+        const float hi = (float)x;
+        dst[(int64_t)b * CHI + col] = hi;
+        if (dstl) dstl[(int64_t)b * CHI + col] = (float)(x - (double)hi);
+      }
     }
     if (wave == 0 && g == 0 && b0 + row < a.B) dste[b0 + row] = (float)(ex + e);
   }
@@ -286,7 +302,14 @@ __device__ __forceinline__ void chain_run(const ChainArgs& a, ChainSmem<CHI>& sm
   for (int e = tid; e < kRB * CHI; e += NT) {
     const int r = e / CHI, i = e % CHI, b = b0 + r;
     double x = 0.0;
-    if (b < a.B) x = a.v_in ? (double)a.v_in[(int64_t)b * CHI + i] : (i == 0 ? 1.0 : 0.0);
+    if (b < a.B) {
+      if (a.v_in) {
+        x = (double)a.v_in[(int64_t)b * CHI + i];
+        if (a.lo) x += (double)a.v_in[vblock_lo(a.B, CHI) + (int64_t)b * CHI + i];
+      } else {
+        x = i == 0 ? 1.0 : 0.0;
+      }
+    }
     sm.vec[0][r][i] = x;
   }
   int ex = (a.v_in && b0 + row < a.B) ? (int)a.v_in[(int64_t)a.B * CHI + b0 + row] : 0;
@@ -624,7 +647,7 @@ int32_t check_sites(const Geometry& g, const tn_tensor* sites, const char* name)
 }
 
 ChainArgs chain_args(const Geometry& g, const tn_tensor* sites, const float* pixels, int step_type, int first_site,
-                     int dir, int n_steps, const float* v_in, float* v_out, float* store) {
+                     int dir, int n_steps, const float* v_in, float* v_out, float* store, int lo) {
   ChainArgs a;
   std::memset(&a, 0, sizeof(a));
   a.first_site = first_site;
@@ -638,6 +661,7 @@ ChainArgs chain_args(const Geometry& g, const tn_tensor* sites, const float* pix
   a.v_in = v_in;
   a.v_out = v_out;
   a.store = store;
+  a.lo = lo;
   a.store_exp = (int64_t)g.E * g.B * g.pad_chi;   // segment buffers: E vector slots, then E x B exponents
   for (int j = 0; j < n_steps; ++j) a.w[j] = static_cast<const float*>(sites[first_site + dir * j].data);
   return a;
@@ -664,9 +688,10 @@ int32_t launch_chains(const Geometry& g, const std::vector<ChainArgs>& runs, hip
 }
 
 int32_t launch_chain(const Geometry& g, const tn_tensor* sites, const float* pixels, int step_type, int first_site,
-                     int dir, int n_steps, const float* v_in, float* v_out, float* store, hipStream_t st) {
+                     int dir, int n_steps, const float* v_in, float* v_out, float* store, int lo, hipStream_t st) {
   if (n_steps <= 0) return TN_OK;
-  return launch_chains(g, {chain_args(g, sites, pixels, step_type, first_site, dir, n_steps, v_in, v_out, store)}, st);
+  return launch_chains(g, {chain_args(g, sites, pixels, step_type, first_site, dir, n_steps, v_in, v_out, store, lo)},
+                       st);
 }
 
 // Weight gradients of one segment: dA_{k_j} = sum_b X_j[b, (a s)] G_j[b, z]
@@ -730,10 +755,10 @@ int32_t forward_core(const Geometry& g, const tn_tensor* sites, const float* pix
     std::vector<ChainArgs> runs;
     if (j < nl)  // slot 0 of each chain (the unit vector) is implicit
       runs.push_back(chain_args(g, sites, pixels, 0, g.left_b[j], 1, g.left_b[j + 1] - g.left_b[j],
-                                j == 0 ? nullptr : ckpt + j * g.vb, ckpt + (j + 1) * g.vb, nullptr));
+                                j == 0 ? nullptr : ckpt + j * g.vb, ckpt + (j + 1) * g.vb, nullptr, 1));
     if (j < nr)
       runs.push_back(chain_args(g, sites, pixels, 1, g.right_b[j] - 1, -1, g.right_b[j] - g.right_b[j + 1],
-                                j == 0 ? nullptr : ckpt + (off + j) * g.vb, ckpt + (off + j + 1) * g.vb, nullptr));
+                                j == 0 ? nullptr : ckpt + (off + j) * g.vb, ckpt + (off + j + 1) * g.vb, nullptr, 1));
     TN_TRY(launch_chains(g, runs, st));
   }
   return TN_OK;
@@ -807,7 +832,7 @@ int32_t tn_mps_classifier_forward(int32_t n_sites, int32_t label_site, int32_t n
     int k = 0, slot = 0;
     while (k < g.c) {
       const int n = std::min(kMaxSeg, g.c - k);
-      TN_TRY(launch_chain(g, sites, px, 0, k, 1, n, prev, local[slot], nullptr, st));
+      TN_TRY(launch_chain(g, sites, px, 0, k, 1, n, prev, local[slot], nullptr, 1, st));
       prev = local[slot];
       slot ^= 1;
       k += n;
@@ -819,7 +844,7 @@ int32_t tn_mps_classifier_forward(int32_t n_sites, int32_t label_site, int32_t n
     slot = 0;
     while (t > g.c + 1) {
       const int n = std::min(kMaxSeg, t - (g.c + 1));
-      TN_TRY(launch_chain(g, sites, px, 1, t - 1, -1, n, prev, uloc[slot], nullptr, st));
+      TN_TRY(launch_chain(g, sites, px, 1, t - 1, -1, n, prev, uloc[slot], nullptr, 1, st));
       prev = uloc[slot];
       slot ^= 1;
       t -= n;
@@ -930,17 +955,17 @@ int32_t tn_mps_classifier_backward(int32_t n_sites, int32_t label_site, int32_t 
       const int s0 = g.left_b[jl], s1 = g.left_b[jl + 1], n = s1 - s0;
       const float* ck = jl == 0 ? nullptr : ckpt + jl * vb;
       // v_{s0} .. v_{s1-1}: step i stores the input of site s0 + i
-      runs.push_back(chain_args(g, sites, px, 0, s0, 1, n, ck, nullptr, segv[0]));
+      runs.push_back(chain_args(g, sites, px, 0, s0, 1, n, ck, nullptr, segv[0], 1));
       // abar_{s1} -> abar_{s0}: step i at site s1-1-i stores abar_{s1-i}
-      runs.push_back(chain_args(g, sites, px, 1, s1 - 1, -1, n, abar, abar, segg[0]));
+      runs.push_back(chain_args(g, sites, px, 1, s1 - 1, -1, n, abar, abar, segg[0], 0));
     }
     if (jr >= 0) {
       const int t0 = g.right_b[jr], t1 = g.right_b[jr + 1], n = t0 - t1;   // sites t1 .. t0-1
       const float* ck = jr == 0 ? nullptr : ckpt + (off + jr) * vb;
       // u_{t0} .. u_{t1+1}: step i at site t0-1-i stores u_{t0-i}
-      runs.push_back(chain_args(g, sites, px, 1, t0 - 1, -1, n, ck, nullptr, segv[1]));
+      runs.push_back(chain_args(g, sites, px, 1, t0 - 1, -1, n, ck, nullptr, segv[1], 1));
       // ubar_{t1} -> ubar_{t0}: step i at site t1+i stores ubar_{t1+i}
-      runs.push_back(chain_args(g, sites, px, 0, t1, 1, n, ubar, ubar, segg[1]));
+      runs.push_back(chain_args(g, sites, px, 0, t1, 1, n, ubar, ubar, segg[1], 0));
     }
     TN_TRY(launch_chains(g, runs, st));
     if (jl >= 0) {

@@ -2,9 +2,12 @@
 // grouped launch used for uneven batches of small problems.
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "gemm_inst.h"
@@ -51,7 +54,7 @@ int grouped_tile_n(int cfg) { return kCfgs[kGroupedCfg[cfg]].bn; }
 
 static GroupedFn pick_grouped(int prec, int cfg, int variant) { return grouped_fn_prec(prec, cfg, variant); }
 
-static int g_forced_cfg = -1;
+static std::atomic<int> g_forced_cfg{-1};
 static std::atomic<int> g_forced_grouped{-1};
 
 int forced_grouped_cfg() { return g_forced_grouped.load(); }
@@ -64,7 +67,8 @@ static bool cfg_allowed(const GemmDesc& d, int c) {
 }
 
 static int heuristic_cfg(const GemmDesc& d) {
-  if (g_forced_cfg >= 0) return g_forced_cfg;
+  const int forced = g_forced_cfg.load();
+  if (forced >= 0) return forced;
   constexpr int kSlots = 256;  // one workgroup per compute unit for the large tiles
   double best = 1e300;
   int best_c = 7;   // 32 x 32 tiles fit every problem
@@ -86,10 +90,62 @@ static int heuristic_cfg(const GemmDesc& d) {
 // ---------------------------------------------------------------------------
 // autotune cache
 
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
 static std::mutex g_tune_mu;
 static int g_tune_level = 0;
-static std::map<std::tuple<int, int, int, int, int, int, int, int, int>, int> g_tune_cache;
+static std::map<TuneKey, int> g_tune_cache;
+static std::string g_tune_path;   // persisted cache file ("" = memory only)
 static thread_local int g_last_choice = -1;
+
+static std::once_flag g_env_once;
+static bool g_log = false;
+
+// "M N K batch amode bmode cmode prec groups -> cfg" per line; caller holds g_tune_mu
+static void load_cache_file_locked() {
+  if (g_tune_path.empty()) return;
+  FILE* f = std::fopen(g_tune_path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    int v[10];
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d -> %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                    &v[7], &v[8], &v[9]) != 10)
+      continue;
+    if (v[9] < 0 || v[9] >= kNumCfgs) continue;
+    g_tune_cache[std::make_tuple(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8])] = v[9];
+  }
+  std::fclose(f);
+}
+
+static void append_cache_file_locked(const TuneKey& k, int cfg) {
+  if (g_tune_path.empty()) return;
+  FILE* f = std::fopen(g_tune_path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d -> %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+               std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), cfg);
+  std::fclose(f);
+}
+
+// starting state from TN_TUNE=off|quick|full, TN_TUNE_CACHE=<path>, TN_LOG=1
+static void read_env() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (const char* t = std::getenv("TN_TUNE")) {
+    if (!std::strcmp(t, "quick") || !std::strcmp(t, "1")) g_tune_level = 1;
+    else if (!std::strcmp(t, "full") || !std::strcmp(t, "2")) g_tune_level = 2;
+    else g_tune_level = 0;
+  }
+  if (const char* c = std::getenv("TN_TUNE_CACHE")) {
+    g_tune_path = c;
+    load_cache_file_locked();
+  }
+  const char* lg = std::getenv("TN_LOG");
+  g_log = lg && lg[0] && std::strcmp(lg, "0") != 0;
+}
+
+bool log_enabled() {
+  std::call_once(g_env_once, read_env);
+  return g_log;
+}
 
 int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st) {
   if (cfg < 0 || cfg >= kNumCfgs) return fail(TN_ERR_INVALID_ARGUMENT, "bad tile config %d", cfg);
@@ -103,7 +159,7 @@ int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st) {
   return hip_check(hipGetLastError(), "gemm launch");
 }
 
-static int tune_cfg(GemmDesc& d, int32_t prec, hipStream_t st) {
+static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return heuristic_cfg(d);
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -118,7 +174,8 @@ static int tune_cfg(GemmDesc& d, int32_t prec, hipStream_t st) {
     if (!cfg_allowed(d, c)) continue;
     if (launch_gemm_cfg(d, prec, c, st) != TN_OK) continue;  // warm-up
     hipEventRecord(e0, st);
-    for (int r = 0; r < 3; ++r) launch_gemm_cfg(d, prec, c, st);
+    const int reps = level >= 2 ? 10 : 3;
+    for (int r = 0; r < reps; ++r) launch_gemm_cfg(d, prec, c, st);
     hipEventRecord(e1, st);
     hipEventSynchronize(e1);
     float ms = 0.f;
@@ -134,30 +191,53 @@ static int tune_cfg(GemmDesc& d, int32_t prec, hipStream_t st) {
 }
 
 int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
-  if (g_forced_cfg < 0 && gemm_small_fits(d)) return launch_gemm_small(d, prec, st);
+  const bool log = log_enabled();
+  const int forced = g_forced_cfg.load();
+  if (forced < 0 && gemm_small_fits(d)) {
+    if (log)
+      std::fprintf(stderr, "[tn] gemm M=%d N=%d K=%d batch=%d prec=%d -> small-extent path\n", d.M, d.N, d.K,
+                   d.batch, (int)prec);
+    return launch_gemm_small(d, prec, st);
+  }
   int cfg;
   int level;
-  auto key = std::make_tuple(d.M, d.N, d.K, d.batch, d.a_mode, d.b_mode, d.c_mode, (int)prec,
-                             (int)(d.gm.n * 100 + d.gn.n * 10 + d.gk.n));
+  const TuneKey key = std::make_tuple(d.M, d.N, d.K, d.batch, d.a_mode, d.b_mode, d.c_mode, (int)prec,
+                                      (int)(d.gm.n * 100 + d.gn.n * 10 + d.gk.n));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     level = g_tune_level;
     auto it = g_tune_cache.find(key);
     cfg = it != g_tune_cache.end() ? it->second : -1;
   }
-  if (g_forced_cfg >= 0) cfg = g_forced_cfg;
-  if (cfg < 0) {
+  const char* how = "cached";
+  if (forced >= 0) {
+    cfg = forced;
+    how = "forced";
+  } else if (cfg < 0) {
+    bool timed = false;
     if (level > 0) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
-        cfg = tune_cfg(d, prec, st);
-      else
+      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+        cfg = tune_cfg(d, prec, level, st);
+        timed = true;
+      } else {
         cfg = heuristic_cfg(d);
+      }
     } else {
       cfg = heuristic_cfg(d);
     }
+    how = timed ? "timed" : "heuristic";
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = cfg;
+    if (timed) append_cache_file_locked(key, cfg);
+  }
+  if (log) {
+    const Cfg& g = kCfgs[cfg];
+    std::fprintf(stderr,
+                 "[tn] gemm M=%d N=%d K=%d batch=%d groups(m,n,k)=(%d,%d,%d) modes(a,b,c)=(%d,%d,%d) prec=%d -> "
+                 "tile %d (%dx%dx%d, %dx%dx%d waves) %s\n",
+                 d.M, d.N, d.K, d.batch, d.gm.n, d.gn.n, d.gk.n, d.a_mode, d.b_mode, d.c_mode, (int)prec, cfg, g.bm,
+                 g.bn, g.bk, g.wm, g.wn, g.wk, how);
   }
   g_last_choice = cfg;
   return launch_gemm_cfg(d, prec, cfg, st);
@@ -189,11 +269,29 @@ int32_t launch_gemm_grouped(const Gemm2D* dev_probs, const int32_t* dev_tile_sta
 
 extern "C" {
 
+int32_t tn_tune(const char* cache_path, int32_t level) {
+  if (level < 0 || level > 2) return tn::fail(TN_ERR_INVALID_ARGUMENT, "tune level %d", level);
+  tn::log_enabled();  // the environment's starting state first, so this call overrides it
+  std::lock_guard<std::mutex> lk(tn::g_tune_mu);
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (!f) return tn::fail(TN_ERR_DEVICE, "cannot open tile cache %s for appending", cache_path);
+    std::fclose(f);
+  }
+  tn::g_tune_level = level;
+  tn::g_tune_cache.clear();
+  tn::g_tune_path = cache_path ? cache_path : "";
+  tn::load_cache_file_locked();
+  return TN_OK;
+}
+
 int32_t tn_tune_set_level(int32_t level) {
   if (level < 0 || level > 1) return tn::fail(TN_ERR_INVALID_ARGUMENT, "tune level %d", level);
+  tn::log_enabled();
   std::lock_guard<std::mutex> lk(tn::g_tune_mu);
   tn::g_tune_level = level;
   tn::g_tune_cache.clear();
+  tn::load_cache_file_locked();
   return TN_OK;
 }
 
@@ -201,8 +299,7 @@ int32_t tn_tune_last_choice(void) { return tn::g_last_choice; }
 
 int32_t tn_tune_force_config(int32_t cfg) {
   if (cfg < -1 || cfg >= tn::kNumCfgs) return tn::fail(TN_ERR_INVALID_ARGUMENT, "tile config %d", cfg);
-  std::lock_guard<std::mutex> lk(tn::g_tune_mu);
-  tn::g_forced_cfg = cfg;
+  tn::g_forced_cfg.store(cfg);
   return TN_OK;
 }
 

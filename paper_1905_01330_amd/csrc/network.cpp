@@ -266,28 +266,10 @@ int32_t build_plan(int32_t n_nodes, const tn_tensor* nodes, const int32_t* label
   return TN_OK;
 }
 
-}  // namespace
-
-}  // namespace tn
-
-using namespace tn;
-
-extern "C" {
-
-int32_t tn_contract_network_workspace(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels,
-                                      const int32_t* offsets, int32_t n_order, const int32_t* order, size_t* bytes) {
-  if (!bytes) return fail(TN_ERR_INVALID_ARGUMENT, "bytes is NULL");
-  Plan plan;
-  TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
-  *bytes = plan.ws_bytes;
-  return TN_OK;
-}
-
-int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels, const int32_t* offsets,
-                            int32_t n_order, const int32_t* order, tn_tensor* out, void* workspace, size_t ws_bytes,
-                            int32_t prec, void* stream) {
-  Plan plan;
-  TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
+// Runs a built plan: validates `out` and the workspace, then one launch
+// sequence per step on `stream`.
+int32_t run_network(const Plan& plan, int32_t n_nodes, const tn_tensor* nodes, tn_tensor* out, void* workspace,
+                    size_t ws_bytes, int32_t prec, void* stream) {
   TN_TRY(check_tensor(out, "out", TN_F32));
   if (plan.ws_bytes > ws_bytes) return fail(TN_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", plan.ws_bytes);
   if (plan.ws_bytes > 0 && !workspace) return fail(TN_ERR_INVALID_ARGUMENT, "workspace is NULL");
@@ -344,6 +326,31 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
     }
   }
   return TN_OK;
+}
+
+}  // namespace
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+int32_t tn_contract_network_workspace(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels,
+                                      const int32_t* offsets, int32_t n_order, const int32_t* order, size_t* bytes) {
+  if (!bytes) return fail(TN_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  Plan plan;
+  TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
+  *bytes = plan.ws_bytes;
+  return TN_OK;
+}
+
+int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels, const int32_t* offsets,
+                            int32_t n_order, const int32_t* order, tn_tensor* out, void* workspace, size_t ws_bytes,
+                            int32_t prec, void* stream) {
+  Plan plan;
+  TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
+  return run_network(plan, n_nodes, nodes, out, workspace, ws_bytes, prec, stream);
 }
 
 }  // extern "C"

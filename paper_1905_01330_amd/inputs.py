@@ -2,8 +2,9 @@
 
 This module only draws random numbers and lays out model constants (the
 Pauli matrices of the spin-chain operators).  It performs none of the
-contraction arithmetic: neither side's result is computed here.  Every array
-is float64 on the host; callers cast and upload as they need.
+contraction arithmetic: neither side's result is computed here.  Arrays are
+float64 on the host (the uneven-batch chains are float32, see uneven_chain);
+callers cast and upload as they need.
 
 Layouts (shared by every consumer):
   * MPS site k:  A_k[D_k, d, D_{k+1}], open boundaries D_0 = D_N = 1.
@@ -67,8 +68,28 @@ def uneven_chain_shapes(n_chains: int = 512, seed: int = 403, n_range=(8, 256), 
 
 
 def uneven_chain(i: int, n_sites: int, chi: int, seed: int = 403, d: int = 2):
-    """Chain i of the uneven batch: a correlated pair seeded by [seed, i]."""
-    return correlated_mps_pair(n_sites, d, chi, [seed, i])
+    """Chain i of the uneven batch: a correlated pair seeded by [seed, i].
+
+    Drawn and combined in float32 (psi = N(0,1) * scale, phi = psi + 0.1 G,
+    each step one IEEE float32 operation), so that the full 512-chain
+    workload (about 84 GB) can be streamed to the device chain by chain in a
+    few tens of seconds while any single chain is reproduced bit for bit.
+    Returns two lists of float32 arrays [D_k, d, D_{k+1}]."""
+    rng = np.random.default_rng([seed, i])
+    dims = bond_dims(n_sites, d, chi)
+    scale = np.float32(1.0 / np.sqrt(chi * d))
+    noise = np.float32(0.1)
+    psi = [rng.standard_normal((dims[k], d, dims[k + 1]), dtype=np.float32) * scale for k in range(n_sites)]
+    phi = [p + noise * (rng.standard_normal(p.shape, dtype=np.float32) * scale) for p in psi]
+    return psi, phi
+
+
+def uneven_chain_flat(i: int, n_sites: int, chi: int, seed: int = 403, d: int = 2):
+    """uneven_chain(i, ...) packed as one float32 buffer: psi's sites then
+    phi's, each site row-major.  Returns (buffer, shapes)."""
+    psi, phi = uneven_chain(i, n_sites, chi, seed, d)
+    shapes = [x.shape for x in psi]
+    return np.concatenate([x.ravel() for x in psi + phi]), shapes
 
 
 # --------------------------------------------------------------------------

@@ -188,3 +188,41 @@ def rel_fro(x, ref):
 def scalar_ms_rel(m, s, m_ref, s_ref):
     """|m e^s / (m_ref e^s_ref) - 1| for (mantissa, log-scale) pairs."""
     return abs(m / m_ref * math.exp(s - s_ref) - 1.0)
+
+
+# --------------------------------------------------------------------------
+# measured-error report (GPU parity runs)
+# --------------------------------------------------------------------------
+
+
+def report(name, **values):
+    """Append one JSON line {"case": name, ...} to $TN_PARITY_REPORT, if set.
+
+    GPU parity tests call this with the errors they measured, so a run can
+    keep the numbers (including those of precisions that are reported but
+    not gated) next to its pass/fail record."""
+    import json
+    import os
+
+    path = os.environ.get("TN_PARITY_REPORT")
+    if not path:
+        return
+    rec = {"case": name}
+    for k, v in values.items():
+        rec[k] = float(v) if isinstance(v, (np.floating, float)) else v
+    with open(path, "a") as f:
+        f.write(json.dumps(rec) + "\n")
+
+
+def energy_abs_scale(psi, mpo, ls_ref, rs_ref):
+    """Sum of |products| of the last contraction on each side (left: L_{N-1}
+    with site N-1, right: R_1 with site 0), from the oracle's environments.
+
+    The energy is one number formed by cancelling sums; its rounding error
+    is bounded relative to this scale, not to |E|."""
+    import oracle
+
+    n = len(psi)
+    el = oracle.env_left_step(np.abs(ls_ref[n - 1]), np.abs(psi[n - 1]), np.abs(mpo[n - 1]))[0, 0, 0]
+    er = oracle.env_right_step(np.abs(rs_ref[1]), np.abs(psi[0]), np.abs(mpo[0]))[0, 0, 0]
+    return float(el), float(er)

@@ -201,3 +201,19 @@ def test_reduce_workspace_constant_matches_header():
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "tn.h")).read()
     m = re.search(r"#define\s+TN_REDUCE_WORKSPACE_BYTES\s+(\d+)", hdr)
     assert m and int(m.group(1)) == L.REDUCE_WORKSPACE_BYTES
+
+
+def test_tune_levels_and_cache_file(tmp_path):
+    lib = L.lib()
+    assert lib.tn_tune(None, 3) == -1
+    assert lib.tn_tune(None, -1) == -1
+    assert lib.tn_tune(str(tmp_path / "no" / "such" / "dir" / "c.txt").encode(), 1) == -6
+    path = tmp_path / "tiles.txt"
+    # a cache with one valid entry, one out-of-range tile and a malformed line
+    path.write_text("384 320 256 1 1 2 1 2 111 -> 3\n1 2 3 4 5 6 7 8 9 -> 999\nnot a line\n")
+    assert lib.tn_tune(str(path).encode(), 2) == 0
+    assert path.read_text().startswith("384 320 256")   # loading never rewrites the file
+    assert lib.tn_tune(None, 0) == 0
+    assert lib.tn_tune_set_level(2) == -1
+    assert lib.tn_tune_set_level(0) == 0
+
