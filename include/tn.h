@@ -137,6 +137,24 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
                             tn_tensor* out, void* workspace, size_t ws_bytes, int32_t prec,
                             void* stream);
 
+/* The same network contraction for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no workspace argument, no allocation of any kind.  The
+ * intermediates and the split-sum scratch live in a static device array of
+ * TN_NOALLOC_SCRATCH_BYTES per GPU (128 MiB), held by every GPU the library
+ * runs on until the process ends; its address is looked up once per device
+ * on the first call there.  Networks whose workspace query
+ * (tn_contract_network_workspace) exceeds that size are rejected with
+ * TN_ERR_UNSUPPORTED before anything runs.  The tile tuner never times
+ * candidates inside this call.  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  Otherwise the
+ * arguments, results and errors are those of tn_contract_network. */
+#define TN_NOALLOC_SCRATCH_BYTES (128u << 20)
+int32_t tn_contract_network_noalloc(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels,
+                                    const int32_t* offsets, int32_t n_order, const int32_t* order,
+                                    tn_tensor* out, int32_t prec, void* stream);
+
 /* Contraction order for the same network description (host only: reads
  * shapes, never data).  method TN_ORDER_GREEDY: repeatedly contract the
  * connected pair of nodes with the fewest flops; TN_ORDER_OPTIMAL: the

@@ -56,6 +56,7 @@ _PROTOS = {
     "tn_outer_product": (I32, [TP, TP, TP, P]),
     "tn_contract_network_workspace": (I32, [I32, TP, I32P, I32P, I32, I32P, C.POINTER(SZ)]),
     "tn_contract_network": (I32, [I32, TP, I32P, I32P, I32, I32P, TP, P, SZ, I32, P]),
+    "tn_contract_network_noalloc": (I32, [I32, TP, I32P, I32P, I32, I32P, TP, I32, P]),
     "tn_network_order": (I32, [I32, TP, I32P, I32P, I32, I32P, I32P, C.POINTER(C.c_double)]),
     "tn_mps_inner_workspace": (I32, [I32, TP, TP, C.POINTER(SZ)]),
     "tn_mps_inner": (I32, [I32, TP, TP, P, P, SZ, I32, P]),

@@ -96,7 +96,10 @@ static int g_tune_level = 0;
 static std::map<TuneKey, int> g_tune_cache;
 static std::string g_tune_path;   // persisted cache file ("" = memory only)
 static thread_local int g_last_choice = -1;
+static thread_local bool g_no_timing = false;
 
+NoTimingScope::NoTimingScope() : prev(g_no_timing) { g_no_timing = true; }
+NoTimingScope::~NoTimingScope() { g_no_timing = prev; }
 static std::once_flag g_env_once;
 static bool g_log = false;
 
@@ -215,7 +218,7 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
     how = "forced";
   } else if (cfg < 0) {
     bool timed = false;
-    if (level > 0) {
+    if (level > 0 && !g_no_timing) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
       if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
         cfg = tune_cfg(d, prec, level, st);

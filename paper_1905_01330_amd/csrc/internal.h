@@ -44,6 +44,14 @@ int32_t reduce_from_axes(const float* x, const float* y, float* out, const std::
 
 // ---- GEMM launch -----------------------------------------------------------
 int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st);
+// While one of these lives on a thread, launch_gemm on that thread never
+// times tile candidates (the cached or heuristic tile is used): timing
+// creates HIP events, which the allocation-free entry points avoid.
+struct NoTimingScope {
+  NoTimingScope();
+  ~NoTimingScope();
+  bool prev;
+};
 // K <= 32 with N or M <= 16 (and no batch, scale or max-abs): the HBM-bound path
 bool gemm_small_fits(const GemmDesc& d);
 int32_t launch_gemm_small(const GemmDesc& d, int32_t prec, hipStream_t st);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -328,6 +329,35 @@ int32_t run_network(const Plan& plan, int32_t n_nodes, const tn_tensor* nodes, t
   return TN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of tn_contract_network_noalloc: a static device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in symbol): each device's
+// address is looked up once, with that device current, and kept.  Nothing
+// in it needs to start at zero (every byte a call reads was written earlier
+// in the same call), and calls that overlap in time on one GPU race on it.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+int32_t noalloc_scratch(void*& out) {
+  int dev = 0;
+  TN_TRY(hip_check(hipGetDevice(&dev), "get device"));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TN_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    TN_TRY(hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address"));
+    if (!p) return fail(TN_ERR_DEVICE, "scratch symbol address is NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  out = g_scratch_ptr[dev];
+  return TN_OK;
+}
+
 }  // namespace
 
 }  // namespace tn
@@ -351,6 +381,23 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
   Plan plan;
   TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
   return run_network(plan, n_nodes, nodes, out, workspace, ws_bytes, prec, stream);
+}
+
+int32_t tn_contract_network_noalloc(int32_t n_nodes, const tn_tensor* nodes, const int32_t* labels,
+                                    const int32_t* offsets, int32_t n_order, const int32_t* order, tn_tensor* out,
+                                    int32_t prec, void* stream) {
+  Plan plan;
+  TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
+  if (plan.ws_bytes > kNoAllocScratchBytes)
+    return fail(TN_ERR_UNSUPPORTED,
+                "network needs %zu bytes of scratch; the library's static scratch holds %zu (use "
+                "tn_contract_network with a caller workspace)",
+                plan.ws_bytes, (size_t)kNoAllocScratchBytes);
+  void* ws = nullptr;
+  if (plan.ws_bytes > 0) TN_TRY(noalloc_scratch(ws));
+  // the tile tuner never times candidates here (timing creates HIP events)
+  NoTimingScope no_timing;
+  return run_network(plan, n_nodes, nodes, out, ws, kNoAllocScratchBytes, prec, stream);
 }
 
 }  // extern "C"

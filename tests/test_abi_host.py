@@ -217,3 +217,21 @@ def test_tune_levels_and_cache_file(tmp_path):
     assert lib.tn_tune_set_level(2) == -1
     assert lib.tn_tune_set_level(0) == 0
 
+
+def test_noalloc_network_rejects_networks_beyond_its_scratch():
+    """a[8192, 8192] . b[8192, 8192] . c[8192] contracted a-b first: the
+    8192 x 8192 intermediate (256 MiB) exceeds the 128 MiB static scratch."""
+    lib = L.lib()
+    n = 8192
+    nodes = (L.TnTensor * 3)()
+    nodes[0], nodes[1], nodes[2] = desc([n, n], A0), desc([n, n], B0), desc([n], O0)
+    labels = L.int_array([-1, 1, 1, 2, 2])
+    offs = L.int_array([0, 2, 4, 5])
+    order = L.int_array([1, 2])
+    out = desc([n], FAKE + (3 << 30))
+    nbytes = C.c_size_t(0)
+    assert lib.tn_contract_network_workspace(3, nodes, labels, offs, 2, order, C.byref(nbytes)) == 0
+    assert nbytes.value > (128 << 20)
+    r = lib.tn_contract_network_noalloc(3, nodes, labels, offs, 2, order, C.byref(out), 0, None)
+    assert r == -3
+    assert b"static scratch" in lib.tn_last_error()
