@@ -13,13 +13,14 @@ GEMM at the bulk-site shape (M = 5120, K = 1024, N = 2048: L_k[1024,5,1024]
 against A_k[1024,2,1024]); its duration is measured with HIP events on the
 stream it runs on, over replays of a HIP graph of that contraction alone
 (`--mode tensordot` issues the same contraction eagerly, for profiling).  `cpu_baseline` times the FP64 oracle
-on a bounded sample of bulk sites of the same sweep.
+on the whole step (both sweeps of the same chain) and compares every
+environment and every headline output with the GPU path's.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode sweep|tensordot|rows|batched|canonicalize]
 
-`--mode batched` and `--mode canonicalize` run one row alone (the uneven batch of
-the first 32 chains in FP32; the FP64 canonicalisation of the chi = 1024 chain),
-for kernel-trace profiles.
+`--mode batched` and `--mode canonicalize` run one row alone (the uneven batch,
+all 512 chains or the first --chains, in --prec; the FP64 canonicalisation of
+the chi = 1024 chain), for kernel-trace profiles.
 """
 from __future__ import annotations
 
@@ -46,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "batched", "canonicalize"], default="sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--chains", type=int, default=512, help="--mode batched: first N chains of the uneven batch")
+    ap.add_argument("--prec", default="fp32", help="--mode batched: precision")
     return ap.parse_args()
 
 
@@ -64,17 +67,50 @@ def sweep_flops(dims, w):
     return f
 
 
-def gpu_inputs(torch, tn, inputs):
+def gpu_inputs(torch, tn, inputs, n_sites=N_SITES, chi=CHI, seed=SEED, model="xxz"):
+    """Random normal MPS, left-canonicalised in FP64 on the GPU and cast to
+    FP32, and the chain's MPO (XXZ with delta = 0.5, or TFIM with J = g = 1)."""
     dev = torch.device("cuda:0")
-    raw = inputs.random_mps(N_SITES, 2, CHI, SEED)
+    raw = inputs.random_mps(n_sites, 2, chi, seed)
     sites64 = [torch.tensor(x, device=dev) for x in raw]
     del raw
     tn.mps_left_canonicalize(sites64)
     psi = [s.float().contiguous() for s in sites64]
     del sites64
-    mpo = [torch.tensor(x, dtype=torch.float32, device=dev) for x in inputs.xxz_mpo(N_SITES, DELTA)]
+    ops = inputs.xxz_mpo(n_sites, DELTA) if model == "xxz" else inputs.tfim_mpo(n_sites)
+    mpo = [torch.tensor(x, dtype=torch.float32, device=dev) for x in ops]
     torch.cuda.synchronize()
     return psi, mpo
+
+
+def load_uneven_batch(torch, inputs, shapes):
+    """All chains of the uneven batch, drawn on the host by a thread pool and
+    copied to the device one chain (one buffer) at a time.  Returns the
+    (psi, phi) site views per chain and the device buffers that own them."""
+    import concurrent.futures as cf
+
+    dev = torch.device("cuda:0")
+    bufs, chains = [], []
+    nthr = max(1, min(16, os.cpu_count() or 1))
+    with cf.ThreadPoolExecutor(nthr) as ex:
+        pending, nxt = {}, 0
+        for i in range(len(shapes)):
+            while nxt < len(shapes) and nxt < i + 2 * nthr:
+                pending[nxt] = ex.submit(inputs.uneven_chain_flat, nxt, *shapes[nxt])
+                nxt += 1
+            flat, sh = pending.pop(i).result()
+            dbuf = torch.from_numpy(flat).to(dev)
+            del flat
+            psi, phi, off = [], [], 0
+            for part in (psi, phi):
+                for s in sh:
+                    cnt = s[0] * s[1] * s[2]
+                    part.append(dbuf[off:off + cnt].view(*s))
+                    off += cnt
+            bufs.append(dbuf)
+            chains.append((psi, phi))
+    torch.cuda.synchronize()
+    return chains, bufs
 
 
 def time_loop(torch, fn, steps, warmup):
@@ -94,28 +130,32 @@ def time_loop(torch, fn, steps, warmup):
 HEAD_REPS = 20  # contractions per recorded graph in the headline loop
 
 
-def headline(torch, tn, steps, warmup, graph=True):
-    """The bulk-site contraction alone, both precisions, with sampled accuracy.
+def headline_operands():
+    """The bulk-site operands L[1024,5,1024] ~ N(0,1) and A[1024,2,1024] ~
+    N(0,1)/sqrt(2048), drawn by numpy (seed 301) as float32."""
+    import numpy as np
+
+    rng = np.random.default_rng(SEED)
+    L = rng.standard_normal((CHI, W_BOND, CHI)).astype(np.float32)
+    A = (rng.standard_normal((CHI, 2, CHI)) / np.sqrt(2 * CHI)).astype(np.float32)
+    return L, A
+
+
+def headline(torch, tn, steps, warmup, graph=True, precs=("split_bf16", "fp32")):
+    """The bulk-site contraction alone, per precision.
 
     With graph=True each timed step replays a HIP graph of HEAD_REPS
     back-to-back contractions, so the per-launch time is the kernel's and
     not the host's issue rate; without it the calls are issued eagerly
-    (the form the kernel-trace profile records)."""
-    import numpy as np
-
+    (the form the kernel-trace profile records).  Returns the outputs too
+    (host float64) for the oracle comparison of the CPU leg."""
     dev = torch.device("cuda:0")
-    g = torch.Generator(device=dev).manual_seed(SEED)
-    L = torch.randn((CHI, W_BOND, CHI), device=dev, generator=g)
-    A = torch.randn((CHI, 2, CHI), device=dev, generator=g) / math.sqrt(2 * CHI)
+    Lh, Ah = headline_operands()
+    L, A = torch.tensor(Lh, device=dev), torch.tensor(Ah, device=dev)
     out = torch.empty((CHI, W_BOND, 2, CHI), device=dev)
     flops = 2.0 * HEAD_M * HEAD_K * HEAD_N
-    res = {}
-    Lh = L.cpu().double().numpy().reshape(HEAD_M, HEAD_K)
-    Ah = A.cpu().double().numpy().reshape(HEAD_K, HEAD_N)
-    rng = np.random.default_rng(0)
-    rows, cols = rng.integers(0, HEAD_M, 4000), rng.integers(0, HEAD_N, 4000)
-    ref = np.einsum("ik,ki->i", Lh[rows], Ah[:, cols])
-    for prec in ("split_bf16", "fp32"):
+    res, outs = {}, {}
+    for prec in precs:
         call = lambda: tn.contract_between(L, A, [2], [0], out=out, prec=prec)  # noqa: E731
         if graph:
             call()  # tile choice for this shape, outside the recording
@@ -123,14 +163,9 @@ def headline(torch, tn, steps, warmup, graph=True):
             ms = time_loop(torch, g.replay, steps, warmup) / HEAD_REPS
         else:
             ms = time_loop(torch, call, steps, warmup)
-        got = out.reshape(HEAD_M, HEAD_N).cpu().double().numpy()[rows, cols]
-        res[prec] = {
-            "ms": ms,
-            "tflops": flops / ms / 1e9,
-            "tile_config": tn.tune_last_choice(),
-            "rel_err_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-        }
-    return flops, res
+        outs[prec] = out.cpu().double().numpy()
+        res[prec] = {"ms": ms, "tflops": flops / ms / 1e9, "tile_config": tn.tune_last_choice()}
+    return flops, res, outs
 
 
 def traffic_for(kernel_key):
@@ -148,40 +183,63 @@ def traffic_for(kernel_key):
         return None
 
 
-def cpu_baseline(inputs):
-    """FP64 oracle on a bounded sample of bulk sites of the same left sweep."""
+def cpu_baseline_and_parity(torch, tn, inputs, head_outs):
+    """The CPU-baseline leg: the FP64 oracle timed on the whole step (left
+    and right sweeps of the same chi = 1024 chain), and the oracle's results
+    compared with the GPU path's: every environment of the sweep in four
+    precisions (on the oracle's own canonical MPS, rounded to FP32 and
+    uploaded) and every output element of the headline contraction."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     import oracle
 
-    dims = inputs.bond_dims(N_SITES, 2, CHI)
+    dev = torch.device("cuda:0")
+    can, _ = oracle.left_canonicalize(inputs.random_mps(N_SITES, 2, CHI, SEED))
+    psi = [x.astype(np.float32).astype(np.float64) for x in can]
+    del can
     mpo = inputs.xxz_mpo(N_SITES, DELTA)
-    rng = np.random.default_rng(SEED)
-    k0, budget_s = 12, 12.0
-    bulk = list(range(k0, N_SITES - 12))       # bulk sites only (D = 1024 on both bonds)
-    l = rng.standard_normal((dims[k0], W_BOND, dims[k0]))
-    fl, n_sample, dt = 0, 0, 0.0
-    while dt < budget_s:                       # cycle over the bulk sites until the budget is spent
-        k = bulk[n_sample % len(bulk)]
-        site = rng.standard_normal((dims[k], 2, dims[k + 1])) / math.sqrt(2 * CHI)
-        t0 = time.perf_counter()
-        l = oracle.env_left_step(l, site, mpo[k])
-        dt += time.perf_counter() - t0
-        l /= np.max(np.abs(l))
-        da, db = dims[k], dims[k + 1]
-        fl += 2 * (da * W_BOND) * da * (2 * db) + 2 * db * (da * 2) * (W_BOND * db) + 2 * da * db * (W_BOND * 2) * (2 * W_BOND)
-        n_sample += 1
+    t0 = time.perf_counter()
+    ls, rs, el, er = oracle.env_sweep(psi, mpo)
+    dt = time.perf_counter() - t0
+    dims = [1] + [x.shape[2] for x in psi]
+    w = [1] + [x.shape[1] for x in mpo]
     threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
-    return {
-        "value": fl / dt / 1e12,
+    base = {
+        "value": sweep_flops(dims, w) / dt / 1e12,
         "unit": "TFLOP/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"{n_sample} left-sweep steps over the bulk sites k={k0}..{N_SITES - 13} (chi=1024, XXZ MPO), "
-                  f"FP64, {dt:.1f} s; numpy BLAS matmul as the oracle's product step",
+        "impl": "numpy FP64; a BLAS matmul is the product step of each tensordot",
+        "sample": f"the whole step: left + right environment sweep of the chi=1024, N=64 XXZ chain, FP64, "
+                  f"{dt:.1f} s on {int(threads)} BLAS threads",
         "seconds": dt,
     }
+    gpsi = [torch.tensor(x, dtype=torch.float32, device=dev) for x in psi]
+    gmpo = [torch.tensor(x, dtype=torch.float32, device=dev) for x in mpo]
+    env_err, energy_err = {}, {}
+    for prec in ("split_bf16", "fp32", "bf16", "split_bf16_3p"):
+        sw = tn.EnvSweep(gpsi, gmpo, left=True, right=True, store=True, prec=prec).run()
+        torch.cuda.synchronize()
+        e = 0.0
+        for k in range(1, N_SITES):
+            for got, ref in ((sw.L[k], ls[k]), (sw.R[k], rs[k])):
+                g = got.cpu().double().numpy()
+                e = max(e, float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+        env_err[prec] = e
+        en = sw.energy.cpu().numpy()
+        energy_err[prec] = max(abs(en[0] - el) / abs(el), abs(en[1] - er) / abs(er))
+        del sw
+    Lh, Ah = headline_operands()
+    ref = oracle.tensordot(Lh, Ah, [2], [0])
+    head_err = {p: float(np.linalg.norm(o - ref) / np.linalg.norm(ref)) for p, o in head_outs.items()}
+    parity = {
+        "oracle": "FP64 numpy oracle, whole outputs (every L_k, R_k with 0 < k < N; every element of T1)",
+        "env_max_rel_err": env_err,
+        "energy_rel_err": energy_err,
+        "headline_rel_err": head_err,
+    }
+    return base, parity
 
 
 # ---------------------------------------------------------------------------
@@ -237,18 +295,22 @@ def rows(torch, tn, inputs):
     out = []
     tn.tune_set_level(1)
 
-    # a1-a4: the two headline tensordots of a bulk site (T1, T3 with its permuted store)
-    L = rn(CHI, W_BOND, CHI)
-    A = rn(CHI, 2, CHI) / math.sqrt(2 * CHI)
-    T2 = rn(CHI, 2, W_BOND, CHI)
+    # a1-a4: the two headline tensordots of a bulk site (T1, T3 with its permuted
+    # store), on the headline's operands and timed as the headline is
+    Lnp, Anp = headline_operands()
+    L, A = torch.tensor(Lnp, device=dev), torch.tensor(Anp, device=dev)
+    T2 = torch.tensor(np.random.default_rng(SEED + 1).standard_normal((CHI, 2, W_BOND, CHI)).astype(np.float32),
+                      device=dev)
     o1 = torch.empty((CHI, W_BOND, 2, CHI), device=dev)
     Lout = torch.empty((CHI, W_BOND, CHI), device=dev)
     o3 = Lout.permute(1, 2, 0)     # T2 . A -> [v, b, b'] stored into L[b', v, b]
     fl = 2.0 * HEAD_M * HEAD_K * HEAD_N
     Lh, Ah, T2h = (x.cpu().double().numpy() for x in (L, A, T2))
     for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
-        ms1 = _gtime(torch, tn, lambda: tn.contract_between(L, A, [2], [0], out=o1, prec=prec))
-        ms3 = _gtime(torch, tn, lambda: tn.contract_between(T2, A, [0, 1], [0, 1], out=o3, prec=prec))
+        ms1 = _gtime(torch, tn, lambda: tn.contract_between(L, A, [2], [0], out=o1, prec=prec), reps=HEAD_REPS,
+                     steps=5, warmup=2)
+        ms3 = _gtime(torch, tn, lambda: tn.contract_between(T2, A, [0, 1], [0, 1], out=o3, prec=prec),
+                     reps=HEAD_REPS, steps=5, warmup=2)
         c1 = _ctime(lambda: oracle.contract_between(Lh[:64], Ah, [(2, 0)]))
         c3 = _ctime(lambda: oracle.contract_between(T2h, Ah[:, :, :64], [(0, 0), (1, 1)]))
         w1 = "L[1024,5,1024] . A[1024,2,1024] over (2,0): M=5120 K=1024 N=2048"
@@ -349,27 +411,49 @@ def rows(torch, tn, inputs):
                     cfl, c, "one bulk left step (FP64)", {"precision": "split_bf16"}))
     del sw
 
-    # a12: uneven batch, the first 32 chains of the 512-chain workload
-    shapes = inputs.uneven_chain_shapes()[:32]
-    chains, bfl = [], 0.0
-    for i, (nn, chi) in enumerate(shapes):
-        p, q = inputs.uneven_chain(i, nn, chi)
-        d_ = [1] + [x.shape[2] for x in p]
+    # a10 at chi = 256: the TFIM sweep, N = 100 (latency-bound sites)
+    del psi
+    psi2, mpo2 = gpu_inputs(torch, tn, inputs, n_sites=100, chi=256, seed=201, model="tfim")
+    d2 = [1] + [int(t.shape[2]) for t in psi2]
+    w2 = [1] + [int(t.shape[1]) for t in mpo2]
+    fl2 = sweep_flops(d2, w2)
+    for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
+        sw2 = tn.EnvSweep(psi2, mpo2, left=True, right=True, store=True, prec=prec)
+        ms = _gtime(torch, tn, sw2.run, reps=2, steps=5, warmup=2)
+        sites = [t.cpu().double().numpy() for t in psi2[50:51]]
+        l2 = np.random.default_rng(0).standard_normal((d2[50], w2[50], d2[50]))
+        mp2 = mpo2[50].cpu().double().numpy()
+        c = _ctime(lambda: oracle.env_left_step(l2, sites[0], mp2))
+        cfl = 2.0 * (d2[50] * w2[50]) * d2[50] * (2 * d2[51]) + 2.0 * d2[51] * (d2[50] * 2) * (w2[51] * d2[51])
+        out.append(_row("a10 chi=256", "environment sweep, left + right", "TFIM, N=100, chi=256, MPO bond 3", fl2, ms,
+                        kind, cfl, c, "one bulk left step (FP64)", {"precision": prec}))
+        del sw2
+    del psi2, mpo2
+
+    # a12: uneven batch, all 512 chains of the workload in one call
+    shapes = inputs.uneven_chain_shapes()
+    chains, keep = load_uneven_batch(torch, inputs, shapes)
+    bfl = 0.0
+    for nn, chi in shapes:
+        d_ = inputs.bond_dims(nn, 2, chi)
         bfl += sum(4.0 * d_[j] ** 2 * d_[j + 1] + 4.0 * d_[j] * d_[j + 1] ** 2 for j in range(nn))
-        chains.append(([torch.tensor(x, dtype=torch.float32, device=dev) for x in p],
-                       [torch.tensor(x, dtype=torch.float32, device=dev) for x in q]))
-    bi = tn.BatchedInner(chains, "fp32")
-    ms = _gtime(torch, tn, bi.run, reps=2)
     cheap = sorted(range(len(shapes)), key=lambda i: shapes[i][0] * shapes[i][1] ** 3)[:4]
     host = [inputs.uneven_chain(i, *shapes[i]) for i in cheap]
+    host = [([x.astype(np.float64) for x in p], [x.astype(np.float64) for x in q]) for p, q in host]
     hfl = 0.0
     for p, q in host:
         d_ = [1] + [x.shape[2] for x in p]
         hfl += sum(4.0 * d_[j] ** 2 * d_[j + 1] + 4.0 * d_[j] * d_[j + 1] ** 2 for j in range(len(p)))
     c = _ctime(lambda: [oracle.mps_inner(p, q) for p, q in host])
-    out.append(_row("a12", "uneven batched inner products, one call", f"first 32 chains of the 512-chain batch "
-                    f"(N ~ U{{8..256}}, chi ~ U{{8..512}})", bfl, ms, "fp32", hfl, c, "the 4 cheapest of the 32 chains (FP64)"))
-    del bi, chains
+    for prec, kind in (("fp32", "fp32"), ("split_bf16", "bf16")):
+        bi = tn.BatchedInner(chains, prec)
+        ms = _gtime(torch, tn, bi.run, reps=1, steps=3, warmup=1)
+        out.append(_row("a12", "uneven batched inner products, one call", "all 512 chains (N ~ U{8..256}, "
+                        "chi ~ U{8..512}, 84 GB)", bfl, ms, kind, hfl, c, "the 4 cheapest chains (FP64)",
+                        {"precision": prec}))
+        del bi
+    del chains, keep
+    torch.cuda.empty_cache()
 
     # a11, a13: classifier forward (cfg4a) and training step (cfg5)
     for tag, (n_, chi, B, seed) in (("cfg4a", (784, 64, 4096, 401)), ("cfg5", (784, 128, 1024, 501))):
@@ -455,15 +539,13 @@ def main():
                   f"{f['bound']} {f['peak']:g} | {f['frac']:.4f} | {o['value']:.3g} {o['unit']} ({o['sample']}) |")
         return
     if a.mode == "batched":
-        dev = torch.device("cuda:0")
-        chains = []
-        for i, (nn, chi) in enumerate(inputs.uneven_chain_shapes()[:32]):
-            p, q = inputs.uneven_chain(i, nn, chi)
-            chains.append(([torch.tensor(x, dtype=torch.float32, device=dev) for x in p],
-                           [torch.tensor(x, dtype=torch.float32, device=dev) for x in q]))
-        bi = tn.BatchedInner(chains, "fp32")
+        shapes = inputs.uneven_chain_shapes()
+        if a.chains < len(shapes):
+            shapes = shapes[:a.chains]
+        chains, keep = load_uneven_batch(torch, inputs, shapes)
+        bi = tn.BatchedInner(chains, a.prec)
         ms = time_loop(torch, bi.run, a.steps, a.warmup)
-        print(json.dumps({"mode": "batched", "chains": 32, "precision": "fp32", "ms_per_call": round(ms, 4)}))
+        print(json.dumps({"mode": "batched", "chains": len(shapes), "precision": a.prec, "ms_per_call": round(ms, 4)}))
         return
     if a.mode == "canonicalize":
         dev = torch.device("cuda:0")
@@ -482,7 +564,7 @@ def main():
         return
     if a.mode == "tensordot":
         tn.tune_set_level(1)
-        flops, res = headline(torch, tn, a.steps, a.warmup, graph=False)
+        flops, res, _ = headline(torch, tn, a.steps, a.warmup, graph=False)
         # a plain 256 MiB device copy in the same process: the reference
         # kernel that calibrates the HBM byte counters
         src = torch.ones(64 << 20, device="cuda:0")
@@ -509,7 +591,8 @@ def main():
     energy = float(sweeps["split_bf16"].energy[0].item())
     e32 = float(sweeps["fp32"].energy[0].item())
 
-    hflops, head = headline(torch, tn, max(a.steps, 5), 2)
+    hflops, head, head_outs = headline(torch, tn, max(a.steps, 5), 2,
+                                       precs=("split_bf16", "fp32", "bf16", "split_bf16_3p"))
     x6 = head["split_bf16"]
     achieved = x6["tflops"]
     traffic = traffic_for("gemm_split_bf16_chi1024")
@@ -552,13 +635,15 @@ def main():
             "headline_frac_of_fp32_peak": round(head["fp32"]["tflops"] / PEAK["fp32"], 4),
         },
         "speedup_split_bf16_vs_fp32": round(ms["fp32"] / ms["split_bf16"], 3),
-        "headline_rel_err": {"split_bf16": x6["rel_err_sampled"], "fp32": head["fp32"]["rel_err_sampled"]},
+        "headline_tflops": {p: round(r["tflops"], 3) for p, r in head.items()},
         "energy": {"split_bf16": energy, "fp32": e32},
         "flops_per_step": flops,
         "graph_replay": {"value": round(flops / (ms_graph * 1e-3) / 1e12, 3), "ms_per_step": round(ms_graph, 4)},
     }
+    del sweeps, gsweep
+    torch.cuda.empty_cache()
     if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(inputs)
+        line["cpu_baseline"], line["parity"] = cpu_baseline_and_parity(torch, tn, inputs, head_outs)
     print(json.dumps(line))
 
 
