@@ -34,3 +34,4 @@ from .classifier import (  # noqa: F401
     classifier_loss_and_grad,
 )
 from .precision import bf16_round, split3, emulate_split_gemm  # noqa: F401
+from .split import split_node, split_node_full_svd, truncation_rank  # noqa: F401
