@@ -302,6 +302,47 @@ int32_t tn_softmax_xent(const tn_tensor* logits, const int64_t* labels, int32_t 
                         tn_tensor* dlogits, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Node splitting (III.B "Node Splitting"; Appendix A "Saving Memory").
+ * The node `a` (TN_F32 or TN_F64, any strides) is read as the matrix
+ * A[(axes 0 .. n_left-1), (axes n_left .. rank-1)] (permute the view to
+ * choose the left and right edges) and decomposed as A = U S V^T in FP64 on
+ * the GPU (one-sided block Jacobi).  The new bond has at most
+ * kmax = min(prod left dims, prod right dims) values.
+ *
+ * tn_split_node_decompose runs the decomposition into `workspace` (size
+ * from tn_split_node_workspace) and applies the truncation rule: keep
+ * k = max(1, min(k_count, k_err)) singular values, with
+ * k_count = min(kmax, max_singular_values) (<= 0: no count limit) and k_err
+ * the smallest k whose dropped values s_k .. s_{kmax-1} add up to at most
+ * max_truncation_err (< 0: no error limit).  It synchronises `stream` once
+ * per Jacobi sweep and at the end, and returns k (and, if `sweeps` is not
+ * NULL, the sweeps run) on the host.  The workspace then holds the
+ * decomposition until it is reused; the writers below read it.
+ *
+ * tn_split_node writes left = U sqrt(S) [left dims..., k] and right =
+ * sqrt(S) V^T [k, right dims...]; tn_split_node_full_svd writes u = U,
+ * s = S ([k] or a [k, k] diagonal matrix) and vh = V^T.  Outputs are
+ * strided views in a's dtype; k may be any value in 1..kmax (normally the
+ * decomposition's).  trun_err (nullable; [kmax - k]) receives the dropped
+ * singular values, largest first.  Singular values are in descending
+ * order (equal values: the order is unspecified); singular vectors of
+ * zero singular values are written as zero.  Asynchronous on `stream`.
+ * Errors: TN_ERR_INVALID_ARGUMENT (n_left outside 1..rank-1, k out of
+ * range), TN_ERR_SHAPE_MISMATCH (an output's extents), TN_ERR_ALIASING
+ * (outputs overlap each other or the node), TN_ERR_UNSUPPORTED (the
+ * shorter effective leg above 16384).
+ * ------------------------------------------------------------------- */
+int32_t tn_split_node_workspace(const tn_tensor* a, int32_t n_left, size_t* bytes);
+int32_t tn_split_node_decompose(const tn_tensor* a, int32_t n_left, int32_t max_singular_values,
+                                double max_truncation_err, int32_t* k, int32_t* sweeps,
+                                void* workspace, size_t ws_bytes, void* stream);
+int32_t tn_split_node(const tn_tensor* a, int32_t n_left, int32_t k, tn_tensor* left, tn_tensor* right,
+                      tn_tensor* trun_err, void* workspace, size_t ws_bytes, void* stream);
+int32_t tn_split_node_full_svd(const tn_tensor* a, int32_t n_left, int32_t k, tn_tensor* u, tn_tensor* s,
+                               tn_tensor* vh, tn_tensor* trun_err, void* workspace, size_t ws_bytes,
+                               void* stream);
+
+/* ---------------------------------------------------------------------
  * Tile autotuner for the contraction GEMM.
  * level 0: heuristic tiles only;
  *       1: on the first contraction of each new (shape, layout, precision)

@@ -19,6 +19,8 @@ from .api import (  # noqa: F401
     network_order,
     outer_product,
     softmax_xent,
+    split_node,
+    split_node_full_svd,
     tensordot,
     trace_edge,
     tune,

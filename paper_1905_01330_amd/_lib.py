@@ -73,6 +73,10 @@ _PROTOS = {
     "tn_mps_classifier_forward": (I32, [I32, I32, I32, TP, TP, TP, P, I32, P, SZ, I32, P]),
     "tn_mps_classifier_backward": (I32, [I32, I32, I32, TP, TP, P, I32, TP, TP, P, SZ, I32, P]),
     "tn_softmax_xent": (I32, [TP, P, I32, P, TP, P, SZ, P]),
+    "tn_split_node_workspace": (I32, [TP, I32, C.POINTER(SZ)]),
+    "tn_split_node_decompose": (I32, [TP, I32, I32, C.c_double, I32P, I32P, P, SZ, P]),
+    "tn_split_node": (I32, [TP, I32, I32, TP, TP, TP, P, SZ, P]),
+    "tn_split_node_full_svd": (I32, [TP, I32, I32, TP, TP, TP, TP, P, SZ, P]),
     "tn_tune": (I32, [C.c_char_p, I32]),
     "tn_tune_set_level": (I32, [I32]),
     "tn_tune_last_choice": (I32, []),

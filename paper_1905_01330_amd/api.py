@@ -254,6 +254,57 @@ def mps_left_canonicalize(sites):
     return lognorm
 
 
+def _split(t, left_axes, right_axes, max_singular_values, max_truncation_err, full):
+    _dev(t)
+    left_axes = [int(x) % t.dim() for x in left_axes]
+    right_axes = [int(x) % t.dim() for x in right_axes]
+    if sorted(left_axes + right_axes) != list(range(t.dim())):
+        raise ValueError("left_axes + right_axes must list every axis of the node once")
+    view = t.permute(*(left_axes + right_axes))
+    n_left = len(left_axes)
+    da = L.tensor_desc(view)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_split_node_workspace(C.byref(da), n_left, C.byref(nbytes)))
+    ws = _workspace(nbytes.value, t.device)
+    k, sweeps = C.c_int32(0), C.c_int32(0)
+    L.check(L.lib().tn_split_node_decompose(C.byref(da), n_left,
+                                            -1 if max_singular_values is None else int(max_singular_values),
+                                            -1.0 if max_truncation_err is None else float(max_truncation_err),
+                                            C.byref(k), C.byref(sweeps), C.c_void_p(ws.data_ptr()), nbytes.value,
+                                            L.stream_ptr()))
+    k = k.value
+    ldims = [view.shape[i] for i in range(n_left)]
+    rdims = [view.shape[i] for i in range(n_left, view.dim())]
+    kmax = min(int(torch.tensor(ldims).prod()), int(torch.tensor(rdims).prod()))
+    left = torch.empty(ldims + [k], dtype=t.dtype, device=t.device)
+    right = torch.empty([k] + rdims, dtype=t.dtype, device=t.device)
+    trun = torch.empty(kmax - k, dtype=t.dtype, device=t.device)
+    dl, dr = L.tensor_desc(left), L.tensor_desc(right)
+    dt = L.tensor_desc(trun) if kmax > k else None
+    tp = C.byref(dt) if dt is not None else None
+    if full:
+        s = torch.empty((k, k), dtype=t.dtype, device=t.device)
+        ds = L.tensor_desc(s)
+        L.check(L.lib().tn_split_node_full_svd(C.byref(da), n_left, k, C.byref(dl), C.byref(ds), C.byref(dr), tp,
+                                               C.c_void_p(ws.data_ptr()), nbytes.value, L.stream_ptr()))
+        return left, s, right, trun
+    L.check(L.lib().tn_split_node(C.byref(da), n_left, k, C.byref(dl), C.byref(dr), tp, C.c_void_p(ws.data_ptr()),
+                                  nbytes.value, L.stream_ptr()))
+    return left, right, trun
+
+
+def split_node(t, left_axes, right_axes, max_singular_values=None, max_truncation_err=None):
+    """Section III.B "Node Splitting": (U sqrt(S), sqrt(S) V^T, trun_err) of the
+    node read as a matrix of its left and right axes, truncated as in
+    Appendix A.  The decomposition synchronises the current stream."""
+    return _split(t, left_axes, right_axes, max_singular_values, max_truncation_err, False)
+
+
+def split_node_full_svd(t, left_axes, right_axes, max_singular_values=None, max_truncation_err=None):
+    """(U, S as a diagonal [k, k] node, V^T, trun_err); see split_node."""
+    return _split(t, left_axes, right_axes, max_singular_values, max_truncation_err, True)
+
+
 def tune(cache_path=None, level: int = 1):
     """Tile autotuner level (0 heuristic, 1 quick, 2 full) and, optionally, a
     text file that persists the tile choices across processes."""

@@ -235,3 +235,29 @@ def test_noalloc_network_rejects_networks_beyond_its_scratch():
     r = lib.tn_contract_network_noalloc(3, nodes, labels, offs, 2, order, C.byref(out), 0, None)
     assert r == -3
     assert b"static scratch" in lib.tn_last_error()
+
+
+def test_split_node_validation_before_launch():
+    lib = L.lib()
+    a = desc([6, 4, 5], A0, dtype=L.F64)
+    nbytes = C.c_size_t(0)
+    assert lib.tn_split_node_workspace(C.byref(a), 0, C.byref(nbytes)) == -1      # no left legs
+    assert lib.tn_split_node_workspace(C.byref(a), 3, C.byref(nbytes)) == -1      # no right legs
+    assert lib.tn_split_node_workspace(C.byref(a), 1, C.byref(nbytes)) == 0 and nbytes.value > 0
+    k = C.c_int32(0)
+    ws = B0
+    assert lib.tn_split_node_decompose(C.byref(a), 1, -1, -1.0, C.byref(k), None, ws, 0, None) == -4
+    assert lib.tn_split_node_decompose(C.byref(a), 1, -1, float("nan"), C.byref(k), None, ws, nbytes.value, None) == -1
+    # writers: k in 1..min(6, 20) and the new bond's extent
+    left, right = desc([6, 3], O0, dtype=L.F64), desc([3, 4, 5], O0 + (1 << 20), dtype=L.F64)
+    assert lib.tn_split_node(C.byref(a), 1, 7, C.byref(left), C.byref(right), None, ws, nbytes.value, None) == -1
+    assert lib.tn_split_node(C.byref(a), 1, 2, C.byref(left), C.byref(right), None, ws, nbytes.value, None) == -2
+    tr = desc([2], O0 + (2 << 20), dtype=L.F64)    # 6 - 3 = 3 dropped values expected
+    assert lib.tn_split_node(C.byref(a), 1, 3, C.byref(left), C.byref(right), C.byref(tr), ws, nbytes.value, None) == -2
+    bad_dtype = desc([6, 3], O0, dtype=L.F32)
+    assert lib.tn_split_node(C.byref(a), 1, 3, C.byref(bad_dtype), C.byref(right), None, ws, nbytes.value, None) == -3
+    overlap = desc([3, 4, 5], O0 + 8, dtype=L.F64)
+    assert lib.tn_split_node(C.byref(a), 1, 3, C.byref(left), C.byref(overlap), None, ws, nbytes.value, None) == -5
+    s_bad = desc([3, 2], O0 + (3 << 20), dtype=L.F64)
+    assert lib.tn_split_node_full_svd(C.byref(a), 1, 3, C.byref(left), C.byref(s_bad), C.byref(right), None, ws,
+                                      nbytes.value, None) == -2
