@@ -343,6 +343,35 @@ int32_t tn_split_node_full_svd(const tn_tensor* a, int32_t n_left, int32_t k, tn
                                void* stream);
 
 /* ---------------------------------------------------------------------
+ * Two-site DMRG update (the algorithm section III.B "Node Splitting" names
+ * as the user of node splitting).  For the two-site tensor theta[a, s1, s2,
+ * b] (TN_F32 [Dl, d1, d2, Dr]) between the left environment L (TN_F32
+ * [Dl, wl, Dl], layout of tn_mps_env_sweep) and the right environment R
+ * ([Dr, wr, Dr]), with the operator sites w1 [wl, wm, d1, d1] and w2
+ * [wm, wr, d2, d2]:
+ *   (H_eff theta)[a', t1, t2, b'] =
+ *     sum L[a', u, a] w1[u, v, t1, s1] w2[v, x, t2, s2] R[b', x, b] theta[a, s1, s2, b]
+ * contracted as one network (L-theta, w1, w2, R) on the contraction kernels
+ * in precision `prec`.
+ * tn_dmrg_apply_heff: out = H_eff theta (out: theta's shape, any strides).
+ * tn_dmrg_eigensolve: the lowest eigenpair of H_eff by Lanczos with full
+ * reorthogonalisation, `krylov` (2..32) vectors per restart, `restarts`
+ * restarts from the Ritz vector; theta (contiguous) is the starting vector
+ * on entry and the normalised eigenvector on return; out2 (DEVICE, 2
+ * doubles) = [energy, |H_eff theta - energy theta|].  No host
+ * synchronisation.  The split of theta into two sites is tn_split_node.
+ * Workspace from tn_dmrg_workspace (it also serves tn_dmrg_apply_heff).
+ * ------------------------------------------------------------------- */
+int32_t tn_dmrg_workspace(const tn_tensor* L, const tn_tensor* R, const tn_tensor* w1, const tn_tensor* w2,
+                          const tn_tensor* theta, int32_t krylov, size_t* bytes);
+int32_t tn_dmrg_apply_heff(const tn_tensor* L, const tn_tensor* R, const tn_tensor* w1, const tn_tensor* w2,
+                           const tn_tensor* theta, tn_tensor* out, void* workspace, size_t ws_bytes, int32_t prec,
+                           void* stream);
+int32_t tn_dmrg_eigensolve(const tn_tensor* L, const tn_tensor* R, const tn_tensor* w1, const tn_tensor* w2,
+                           tn_tensor* theta, int32_t krylov, int32_t restarts, double* out2, void* workspace,
+                           size_t ws_bytes, int32_t prec, void* stream);
+
+/* ---------------------------------------------------------------------
  * Tile autotuner for the contraction GEMM.
  * level 0: heuristic tiles only;
  *       1: on the first contraction of each new (shape, layout, precision)

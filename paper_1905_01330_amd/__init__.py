@@ -12,6 +12,10 @@ from .api import (  # noqa: F401
     Graph,
     contract_between,
     contract_network,
+    dmrg,
+    dmrg_apply_heff,
+    dmrg_eigensolve,
+    dmrg_two_site_update,
     mps_env_sweep,
     mps_inner,
     mps_inner_batched,

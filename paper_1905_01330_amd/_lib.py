@@ -77,6 +77,9 @@ _PROTOS = {
     "tn_split_node_decompose": (I32, [TP, I32, I32, C.c_double, I32P, I32P, P, SZ, P]),
     "tn_split_node": (I32, [TP, I32, I32, TP, TP, TP, P, SZ, P]),
     "tn_split_node_full_svd": (I32, [TP, I32, I32, TP, TP, TP, TP, P, SZ, P]),
+    "tn_dmrg_workspace": (I32, [TP, TP, TP, TP, TP, I32, C.POINTER(SZ)]),
+    "tn_dmrg_apply_heff": (I32, [TP, TP, TP, TP, TP, TP, P, SZ, I32, P]),
+    "tn_dmrg_eigensolve": (I32, [TP, TP, TP, TP, TP, I32, I32, P, P, SZ, I32, P]),
     "tn_tune": (I32, [C.c_char_p, I32]),
     "tn_tune_set_level": (I32, [I32]),
     "tn_tune_last_choice": (I32, []),

@@ -305,6 +305,95 @@ def split_node_full_svd(t, left_axes, right_axes, max_singular_values=None, max_
     return _split(t, left_axes, right_axes, max_singular_values, max_truncation_err, True)
 
 
+# ---------------------------------------------------------------------------
+# two-site DMRG
+
+
+def _dmrg_descs(L_, R_, W1, W2, theta):
+    return [L.tensor_desc(x) for x in (L_, R_, W1, W2, theta)]
+
+
+def dmrg_apply_heff(L_, R_, W1, W2, theta, out=None, prec="fp32", krylov=2):
+    """H_eff theta for the two-site tensor theta[a, s1, s2, b]."""
+    if out is None:
+        out = torch.empty_like(theta)
+    dl, dr, d1, d2, dt = _dmrg_descs(L_, R_, W1, W2, theta)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_dmrg_workspace(C.byref(dl), C.byref(dr), C.byref(d1), C.byref(d2), C.byref(dt), krylov,
+                                      C.byref(nbytes)))
+    ws = _workspace(nbytes.value, theta.device)
+    do = L.tensor_desc(out)
+    L.check(L.lib().tn_dmrg_apply_heff(C.byref(dl), C.byref(dr), C.byref(d1), C.byref(d2), C.byref(dt), C.byref(do),
+                                       C.c_void_p(ws.data_ptr()), nbytes.value, L.prec_code(prec), L.stream_ptr()))
+    return out
+
+
+def dmrg_eigensolve(L_, R_, W1, W2, theta, krylov=24, restarts=3, prec="fp32"):
+    """Lowest eigenpair of H_eff by Lanczos; theta (contiguous) is the start and
+    becomes the eigenvector.  Returns a device float64 tensor [energy, residual]."""
+    dl, dr, d1, d2, dt = _dmrg_descs(L_, R_, W1, W2, theta)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_dmrg_workspace(C.byref(dl), C.byref(dr), C.byref(d1), C.byref(d2), C.byref(dt), krylov,
+                                      C.byref(nbytes)))
+    ws = _workspace(nbytes.value, theta.device)
+    out2 = torch.empty(2, dtype=torch.float64, device=theta.device)
+    L.check(L.lib().tn_dmrg_eigensolve(C.byref(dl), C.byref(dr), C.byref(d1), C.byref(d2), C.byref(dt), krylov,
+                                       restarts, C.c_void_p(out2.data_ptr()), C.c_void_p(ws.data_ptr()), nbytes.value,
+                                       L.prec_code(prec), L.stream_ptr()))
+    return out2
+
+
+def dmrg_two_site_update(L_, R_, W1, W2, theta, chi_max=None, direction="right", krylov=24, restarts=3,
+                         prec="fp32", max_truncation_err=None):
+    """One two-site DMRG update: the lowest eigenvector of H_eff (theta is the
+    starting vector and is overwritten), split with truncation.  direction
+    "right": (U, S V^T); "left": (U S, V^T).  Returns (energy/residual device
+    tensor, a_left, a_right, trun_err)."""
+    out2 = dmrg_eigensolve(L_, R_, W1, W2, theta, krylov, restarts, prec)
+    u, s, vt, trun = split_node_full_svd(theta, [0, 1], [2, 3], chi_max, max_truncation_err)
+    if direction == "right":
+        return out2, u, contract_between(s, vt, [1], [0], prec="fp32"), trun
+    return out2, contract_between(u, s, [2], [0], prec="fp32"), vt, trun
+
+
+_ENV_LEFT = ([[1, 2, 3], [3, 4, -3], [2, -2, 5, 4], [1, 5, -1]], [3, 2, 4, 1, 5])
+_ENV_RIGHT = ([[1, 2, 3], [-3, 4, 3], [-2, 2, 5, 4], [-1, 5, 1]], [3, 2, 4, 1, 5])
+
+
+def _theta_of(a, b, prec):
+    return contract_between(a, b, [2], [0], prec=prec).contiguous()
+
+
+def dmrg(mpo, psi, chi_max, sweeps=2, krylov=24, restarts=2, prec="fp32"):
+    """Two-site DMRG for the ground state of an MPO (lists of device FP32
+    tensors).  psi must be left-canonical (tn_mps_left_canonicalize gives
+    one); it is updated in place, sweeping right to left, then left to right.
+    Environments are updated with tn_contract_network steps.  Returns the
+    energy after every update (a host list) and psi."""
+    n = len(psi)
+    ls, _, _ = mps_env_sweep(psi, mpo, left=True, right=False, store=True, prec=prec)
+    rs = [None] * (n + 1)
+    rs[n] = torch.ones((1, 1, 1), device=psi[0].device)
+    energies = []
+    for _ in range(sweeps):
+        for k in range(n - 2, -1, -1):
+            th = _theta_of(psi[k], psi[k + 1], prec)
+            out2, a, b, _ = dmrg_two_site_update(ls[k], rs[k + 2], mpo[k], mpo[k + 1], th, chi_max, "left",
+                                                 krylov, restarts, prec)
+            psi[k], psi[k + 1] = a, b
+            rs[k + 1] = contract_network([rs[k + 2], b, mpo[k + 1], b], _ENV_RIGHT[0], order=_ENV_RIGHT[1],
+                                         prec=prec)
+            energies.append(float(out2[0].cpu()))
+        for k in range(0, n - 1):
+            th = _theta_of(psi[k], psi[k + 1], prec)
+            out2, a, b, _ = dmrg_two_site_update(ls[k], rs[k + 2], mpo[k], mpo[k + 1], th, chi_max, "right",
+                                                 krylov, restarts, prec)
+            psi[k], psi[k + 1] = a, b
+            ls[k + 1] = contract_network([ls[k], a, mpo[k], a], _ENV_LEFT[0], order=_ENV_LEFT[1], prec=prec)
+            energies.append(float(out2[0].cpu()))
+    return energies, psi
+
+
 def tune(cache_path=None, level: int = 1):
     """Tile autotuner level (0 heuristic, 1 quick, 2 full) and, optionally, a
     text file that persists the tile choices across processes."""

@@ -261,3 +261,21 @@ def test_split_node_validation_before_launch():
     s_bad = desc([3, 2], O0 + (3 << 20), dtype=L.F64)
     assert lib.tn_split_node_full_svd(C.byref(a), 1, 3, C.byref(left), C.byref(s_bad), C.byref(right), None, ws,
                                       nbytes.value, None) == -2
+
+
+def test_dmrg_validation_and_workspace_on_host():
+    """The effective-Hamiltonian network is planned on the host: the
+    workspace query succeeds for consistent shapes and rejects others."""
+    lib = L.lib()
+    Lt, Rt = desc([8, 3, 8], A0), desc([6, 3, 6], A0 + (1 << 20))
+    w1, w2 = desc([3, 3, 2, 2], A0 + (2 << 20)), desc([3, 3, 2, 2], A0 + (3 << 20))
+    th = desc([8, 2, 2, 6], B0)
+    nbytes = C.c_size_t(0)
+    assert lib.tn_dmrg_workspace(C.byref(Lt), C.byref(Rt), C.byref(w1), C.byref(w2), C.byref(th), 24,
+                                 C.byref(nbytes)) == 0
+    assert nbytes.value > 33 * 8 * 2 * 2 * 6 * 4
+    assert lib.tn_dmrg_workspace(C.byref(Lt), C.byref(Rt), C.byref(w1), C.byref(w2), C.byref(th), 40,
+                                 C.byref(nbytes)) == -1
+    bad = desc([8, 2, 2, 7], B0)
+    assert lib.tn_dmrg_workspace(C.byref(Lt), C.byref(Rt), C.byref(w1), C.byref(w2), C.byref(bad), 24,
+                                 C.byref(nbytes)) == -2
