@@ -226,3 +226,51 @@ def energy_abs_scale(psi, mpo, ls_ref, rs_ref):
     el = oracle.env_left_step(np.abs(ls_ref[n - 1]), np.abs(psi[n - 1]), np.abs(mpo[n - 1]))[0, 0, 0]
     er = oracle.env_right_step(np.abs(rs_ref[1]), np.abs(psi[0]), np.abs(mpo[0]))[0, 0, 0]
     return float(el), float(er)
+
+
+# --------------------------------------------------------------------------
+# contraction order for the oracle on large networks (test side, independent
+# of the library's own search)
+# --------------------------------------------------------------------------
+
+
+def greedy_order(shapes, labels):
+    """A label order for oracle.contract_network: repeatedly join the two
+    connected nodes whose joint result has the fewest elements (ties: the
+    pair found first).  Trace labels come first.  Plain Python over the
+    structure only."""
+    nodes = [dict(zip(map(int, l), map(int, s))) for s, l in zip(shapes, labels)]
+    order = []
+    # traces: a label twice on one node
+    for i, l in enumerate(labels):
+        dup = {x for x in l if list(l).count(x) == 2 and x >= 0}
+        order.extend(sorted(dup))
+    live = [dict(nd) for nd in nodes]
+    alive = list(range(len(live)))
+    while True:
+        best = None
+        for ai in range(len(alive)):
+            for bi in range(ai + 1, len(alive)):
+                a, b = live[alive[ai]], live[alive[bi]]
+                shared = [x for x in a if x in b]
+                if not shared:
+                    continue
+                size = 1
+                for x, dx in a.items():
+                    if x not in b:
+                        size *= dx
+                for x, dx in b.items():
+                    if x not in a:
+                        size *= dx
+                if best is None or size < best[0]:
+                    best = (size, ai, bi, shared)
+        if best is None:
+            break
+        _, ai, bi, shared = best
+        ia, ib = alive[ai], alive[bi]
+        order.extend(sorted(shared))
+        merged = {x: dx for x, dx in live[ia].items() if x not in live[ib]}
+        merged.update({x: dx for x, dx in live[ib].items() if x not in live[ia]})
+        live.append(merged)
+        alive = [k for k in alive if k not in (ia, ib)] + [len(live) - 1]
+    return order
