@@ -157,7 +157,10 @@ int32_t tn_contract_network_noalloc(int32_t n_nodes, const tn_tensor* nodes, con
 
 /* Contraction order for the same network description (host only: reads
  * shapes, never data).  method TN_ORDER_GREEDY: repeatedly contract the
- * connected pair of nodes with the fewest flops; TN_ORDER_OPTIMAL: the
+ * connected pair of nodes that is best by one criterion (fewest flops;
+ * largest shrink of the network, i.e. result size minus operand sizes;
+ * smallest result), one pass per criterion, keeping the pass with the
+ * fewest total flops; TN_ORDER_OPTIMAL: the
  * exact minimum total flops over all pairwise contraction trees (dynamic
  * programming over node subsets, at most 12 nodes per connected component,
  * else TN_ERR_UNSUPPORTED).  Cost of a pairwise step: 2 x the product of the

@@ -3,8 +3,10 @@
 // every label on the two nodes (contracted labels once): the product
 // C = sum_k A B over all shared labels, as the network driver contracts it.
 // Labels traced on one node are contracted first (they shrink that node).
-//   greedy : repeatedly contract the connected pair of nodes with the fewest
-//            flops (ties: the smaller result, then the lower node indices);
+//   greedy : repeatedly contract the connected pair of nodes that is best by
+//            one criterion (fewest flops; largest shrink of the network,
+//            i.e. result size minus operand sizes; smallest result), one
+//            pass per criterion, keeping the pass with the fewest total flops;
 //   optimal: exact minimum total flops over all pairwise contraction trees
 //            (dynamic programming over subsets of each connected component,
 //            at most 12 nodes per component), merging only node sets that
@@ -95,23 +97,30 @@ double size_of(const OrderNet& net, const std::vector<int32_t>& ls) {
   return s;
 }
 
-void greedy(const OrderNet& net, std::vector<int32_t>& order, double& flops) {
+// One greedy pass.  criterion 0: the pair with the fewest flops; 1: the pair
+// whose result shrinks the network most (result size minus the two
+// operands' sizes); 2: the pair with the smallest result.  Ties: fewer
+// flops, then the lower node indices.
+void greedy_pass(const OrderNet& net, int criterion, std::vector<int32_t>& order, double& flops) {
   std::vector<std::vector<int32_t>> alive = net.labels;
   std::vector<bool> gone(alive.size(), false);
   for (;;) {
     int bi = -1, bj = -1;
-    double bf = 0.0, bs = 0.0;
+    double bkey = 0.0, bf = 0.0;
     for (size_t i = 0; i < alive.size(); ++i) {
       if (gone[i]) continue;
       for (size_t j = i + 1; j < alive.size(); ++j) {
         if (gone[j] || shared_label(alive[i], alive[j]) == INT32_MIN) continue;
         const double f = pair_flops(net, alive[i], alive[j]);
         const double s = size_of(net, merged(alive[i], alive[j]));
-        if (bi < 0 || f < bf || (f == bf && s < bs)) {
+        const double key = criterion == 0 ? f
+                         : criterion == 1 ? s - size_of(net, alive[i]) - size_of(net, alive[j])
+                                          : s;
+        if (bi < 0 || key < bkey || (key == bkey && f < bf)) {
           bi = (int)i;
           bj = (int)j;
+          bkey = key;
           bf = f;
-          bs = s;
         }
       }
     }
@@ -121,6 +130,23 @@ void greedy(const OrderNet& net, std::vector<int32_t>& order, double& flops) {
     alive[bi] = merged(alive[bi], alive[bj]);
     gone[bj] = true;
   }
+}
+
+// the cheapest (total flops) of the three greedy passes
+void greedy(const OrderNet& net, std::vector<int32_t>& order, double& flops) {
+  std::vector<int32_t> best;
+  double best_f = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    std::vector<int32_t> o;
+    double f = 0.0;
+    greedy_pass(net, c, o, f);
+    if (c == 0 || f < best_f) {
+      best = o;
+      best_f = f;
+    }
+  }
+  order.insert(order.end(), best.begin(), best.end());
+  flops += best_f;
 }
 
 constexpr int kMaxOptimal = 12;
