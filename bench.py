@@ -16,7 +16,11 @@ stream it runs on, over replays of a HIP graph of that contraction alone
 on the whole step (both sweeps of the same chain) and compares every
 environment and every headline output with the GPU path's.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode sweep|tensordot|rows|batched|canonicalize]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode sweep|tensordot|rows|next|batched|canonicalize]
+
+`--mode rows` times every row of the chain path against its roofline and `--mode next` the rows
+beyond it (split_node, a two-site DMRG update, TTN and MERA networks), each with the oracle timed
+beside it on a bounded sample.
 
 `--mode batched` and `--mode canonicalize` run one row alone (the uneven batch,
 all 512 chains or the first --chains, in --prec; the FP64 canonicalisation of
@@ -45,7 +49,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "batched", "canonicalize"], default="sweep")
+    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "next", "batched", "canonicalize"],
+                    default="sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--chains", type=int, default=512, help="--mode batched: first N chains of the uneven batch")
     ap.add_argument("--prec", default="fp32", help="--mode batched: precision")
@@ -515,6 +520,101 @@ def rows(torch, tn, inputs):
     return out
 
 
+def next_rows(torch, tn, inputs):
+    """Rows beyond the chain networks: node splitting (the paper's 1000 x 1000
+    truncation example), one two-site DMRG update at chi = 256, and the
+    TTN / MERA expectation networks, each against its roofline with the
+    oracle timed beside it on a bounded sample."""
+    import numpy as np
+
+    import oracle
+    from paper_1905_01330_amd import networks
+
+    dev = torch.device("cuda:0")
+    out = []
+    rng = np.random.default_rng(SEED)
+
+    # split_node of a 1000 x 1000 node (FP64), max_singular_values = 5
+    n = 1000
+    q1 = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    q2 = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    a = (q1 * np.exp(-np.arange(n) / 40.0)[None, :]) @ q2.T
+    ga = torch.tensor(a, device=dev)
+    tn.split_node(ga, [0], [1], max_singular_values=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        tn.split_node(ga, [0], [1], max_singular_values=5)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    svd_flops = 4.0 * n * n * n + 8.0 * n * n * n + 9.0 * n ** 3   # thin SVD with both factors (Golub and Van Loan)
+    c = _ctime(lambda: oracle.split_node(a, 1, max_singular_values=5))
+    out.append(_row("n1", "split_node, FP64 one-sided block Jacobi SVD + truncation", "1000 x 1000 node, "
+                    "max_singular_values=5 (Appendix A example)", svd_flops, ms, "fp64", svd_flops, c,
+                    "the same node (numpy LAPACK SVD)", {"note": "host-timed; synchronising call"}))
+
+    # one two-site DMRG update at chi = 256 (TFIM, bulk sites of the N = 100 chain)
+    psi, mpo = gpu_inputs(torch, tn, inputs, n_sites=100, chi=256, seed=201, model="tfim")
+    ls, _, _ = tn.mps_env_sweep(psi, mpo, left=True, right=False, store=True)
+    _, rs, _ = tn.mps_env_sweep(psi, mpo, left=False, right=True, store=True)
+    k = 50
+    theta0 = tn.contract_between(psi[k], psi[k + 1], [2], [0]).contiguous()
+    shapes, labels = [tuple(x.shape) for x in (ls[k], theta0, mpo[k], mpo[k + 1], rs[k + 2])], \
+        [[-1, 1, 2], [2, 3, 4, 5], [1, 6, -2, 3], [6, 7, -3, 4], [-4, 7, 5]]
+    _, mv_flops = tn.network_order([ls[k], theta0, mpo[k], mpo[k + 1], rs[k + 2]], labels, "greedy")
+    for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
+        th = theta0.clone()
+        tn.dmrg_two_site_update(ls[k], rs[k + 2], mpo[k], mpo[k + 1], th, chi_max=256, krylov=24, restarts=2,
+                                prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = theta0.clone()
+        out2, _, _, _ = tn.dmrg_two_site_update(ls[k], rs[k + 2], mpo[k], mpo[k + 1], th, chi_max=256, krylov=24,
+                                                restarts=2, prec=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        n_mv = 24 * 2 + 1
+        fl = mv_flops * n_mv
+        lh = ls[k][:64, :, :64].cpu().double().numpy()
+        rh = rs[k + 2][:64, :, :64].cpu().double().numpy()
+        th_h = np.random.default_rng(0).standard_normal((64, 2, 2, 64))
+        w1, w2 = mpo[k].cpu().double().numpy(), mpo[k + 1].cpu().double().numpy()
+        cc = _ctime(lambda: oracle.heff_apply(lh, rh, w1, w2, th_h))
+        cfl = mv_flops * (64 / 256) ** 3
+        out.append(_row("n3", "two-site DMRG update: 49 H_eff mat-vecs (Lanczos, 24 vectors, 2 restarts) + split",
+                        "TFIM N=100, chi=256, sites 50-51", fl, ms, kind, cfl, cc,
+                        "one H_eff mat-vec at chi=64 (FP64)",
+                        {"precision": prec, "energy": float(out2[0].cpu()), "residual": float(out2[1].cpu()),
+                         "note": "host-timed, includes the synchronising split; flops count the mat-vecs only"}))
+    del psi, mpo, ls, rs
+
+    # TTN (N = 256, chi = 64) and binary MERA (N = 16, chi = 16): <Z Z> on two middle sites
+    zz = np.diag([1.0, -1.0])
+    for name, nn, chi, mera, csample in (("n4 TTN", 256, 64, False, (64, 32)), ("n4 MERA", 16, 16, True, (16, 4))):
+        mid = nn // 2 - 1
+        shapes, labels, src = networks.expectation(nn, 2, chi, (mid, mid + 1), mera)
+        net, _ = networks.tree_state(nn, 2, chi, mera)
+        g = np.random.default_rng(7)
+        state = [torch.tensor(g.standard_normal(s) / np.sqrt(s[0] * s[1]), dtype=torch.float32, device=dev)
+                 for s in net.shapes]
+        zt = torch.tensor(zz, dtype=torch.float32, device=dev)
+        nodes = [state[i] if i >= 0 else zt for i in src]
+        order, fl = tn.network_order(nodes, labels, "greedy")
+        sh, sl, ss = networks.expectation(csample[0], 2, csample[1], (3, 4), mera)
+        snet, _ = networks.tree_state(csample[0], 2, csample[1], mera)
+        hs = [g.standard_normal(s) / np.sqrt(s[0] * s[1]) for s in snet.shapes]
+        hn = [hs[i] if i >= 0 else zz for i in ss]
+        horder, hfl = tn.network_order([torch.empty(s) for s in sh], sl, "greedy")
+        c = _ctime(lambda: oracle.contract_network(hn, sl, horder))
+        for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
+            ms = _gtime(torch, tn, lambda: tn.contract_network(nodes, labels, order=order, prec=prec), reps=2)
+            out.append(_row(name, f"<psi|Z Z|psi> network ({len(nodes)} nodes, greedy order)",
+                            f"N={nn}, chi={chi}, d=2", fl, ms, kind, hfl, c,
+                            f"N={csample[0]}, chi={csample[1]} (FP64, the same order search)", {"precision": prec}))
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -526,8 +626,8 @@ def main():
     import paper_1905_01330_amd as tn
     from paper_1905_01330_amd import inputs
 
-    if a.mode == "rows":
-        res = rows(torch, tn, inputs)
+    if a.mode in ("rows", "next"):
+        res = rows(torch, tn, inputs) if a.mode == "rows" else next_rows(torch, tn, inputs)
         for r in res:
             print(json.dumps(r))
         print("| row | workload | ms | achieved | roofline | frac | oracle (sample) |")

@@ -10,7 +10,8 @@
 //   optimal: exact minimum total flops over all pairwise contraction trees
 //            (dynamic programming over subsets of each connected component,
 //            at most 12 nodes per component), merging only node sets that
-//            share a label, as the driver does.
+//            share a label, as the driver does, and whose result keeps at
+//            most TN_MAX_RANK axes.
 // The result is a label order for tn_contract_network: per merge, one label
 // shared by the two sides (the driver contracts the others with it).
 #include <algorithm>
@@ -100,51 +101,83 @@ double size_of(const OrderNet& net, const std::vector<int32_t>& ls) {
 // One greedy pass.  criterion 0: the pair with the fewest flops; 1: the pair
 // whose result shrinks the network most (result size minus the two
 // operands' sizes); 2: the pair with the smallest result.  Ties: fewer
-// flops, then the lower node indices.
-void greedy_pass(const OrderNet& net, int criterion, std::vector<int32_t>& order, double& flops) {
+// flops, then the lower node indices.  strict: pairs whose result has more
+// axes than a tensor descriptor holds are never taken, and the pass fails
+// (returns false) when only such pairs are left; otherwise they are taken
+// only when no other pair joins.  seed != 0: pick at random (a fixed
+// linear congruential sequence) among the `pool` best pairs.
+bool greedy_pass(const OrderNet& net, int criterion, bool strict, uint32_t seed, int pool, std::vector<int32_t>& order,
+                 double& flops) {
   std::vector<std::vector<int32_t>> alive = net.labels;
   std::vector<bool> gone(alive.size(), false);
+  uint32_t rnd = seed;
+  struct Cand {
+    double key, f;
+    bool over;
+    int i, j;
+  };
   for (;;) {
-    int bi = -1, bj = -1;
-    double bkey = 0.0, bf = 0.0;
+    std::vector<Cand> best;   // up to `pool`, best first
+    bool any_pair = false;
     for (size_t i = 0; i < alive.size(); ++i) {
       if (gone[i]) continue;
       for (size_t j = i + 1; j < alive.size(); ++j) {
         if (gone[j] || shared_label(alive[i], alive[j]) == INT32_MIN) continue;
+        any_pair = true;
+        const std::vector<int32_t> m = merged(alive[i], alive[j]);
+        const bool over = (int)m.size() > TN_MAX_RANK;
+        if (over && strict) continue;
         const double f = pair_flops(net, alive[i], alive[j]);
-        const double s = size_of(net, merged(alive[i], alive[j]));
+        const double sz = size_of(net, m);
         const double key = criterion == 0 ? f
-                         : criterion == 1 ? s - size_of(net, alive[i]) - size_of(net, alive[j])
-                                          : s;
-        if (bi < 0 || key < bkey || (key == bkey && f < bf)) {
-          bi = (int)i;
-          bj = (int)j;
-          bkey = key;
-          bf = f;
+                         : criterion == 1 ? sz - size_of(net, alive[i]) - size_of(net, alive[j])
+                                          : sz;
+        const Cand c{key, f, over, (int)i, (int)j};
+        auto better = [](const Cand& x, const Cand& y) {
+          if (x.over != y.over) return !x.over;
+          return x.key < y.key || (x.key == y.key && x.f < y.f);
+        };
+        size_t pos = best.size();
+        while (pos > 0 && better(c, best[pos - 1])) --pos;
+        if ((int)pos < pool) {
+          best.insert(best.begin() + pos, c);
+          if ((int)best.size() > pool) best.pop_back();
         }
       }
     }
-    if (bi < 0) break;
-    order.push_back(shared_label(alive[bi], alive[bj]));
-    flops += bf;
-    alive[bi] = merged(alive[bi], alive[bj]);
-    gone[bj] = true;
+    if (best.empty()) return !any_pair;   // done, or only over-rank pairs left (strict)
+    size_t pick = 0;
+    if (seed) {
+      rnd = rnd * 1664525u + 1013904223u;
+      pick = (rnd >> 16) % best.size();
+    }
+    const Cand& c = best[pick];
+    order.push_back(shared_label(alive[c.i], alive[c.j]));
+    flops += c.f;
+    alive[c.i] = merged(alive[c.i], alive[c.j]);
+    gone[c.j] = true;
   }
 }
 
-// the cheapest (total flops) of the three greedy passes
+// The cheapest (total flops) order among: the three strict passes; if none
+// completes, 256 seeded random strict passes (the three criteria in turn,
+// picking among the best 3 to 5 pairs); if none completes either, the three
+// permissive passes (the driver then rejects the over-rank step).
 void greedy(const OrderNet& net, std::vector<int32_t>& order, double& flops) {
   std::vector<int32_t> best;
-  double best_f = 0.0;
-  for (int c = 0; c < 3; ++c) {
+  double best_f = INFINITY;
+  auto consider = [&](int c, bool strict, uint32_t seed, int pool) {
     std::vector<int32_t> o;
     double f = 0.0;
-    greedy_pass(net, c, o, f);
-    if (c == 0 || f < best_f) {
+    if (greedy_pass(net, c, strict, seed, pool, o, f) && f < best_f) {
       best = o;
       best_f = f;
     }
-  }
+  };
+  for (int c = 0; c < 3; ++c) consider(c, true, 0, 1);
+  for (uint32_t t = 1; best_f == INFINITY && t <= 256; ++t)
+    consider((int)(t % 3), true, 0x9e3779b9u * t, 3 + (int)(t % 3));
+  for (int c = 0; best_f == INFINITY && c < 3; ++c) consider(c, false, 0, 1);
   order.insert(order.end(), best.begin(), best.end());
   flops += best_f;
 }
@@ -152,7 +185,8 @@ void greedy(const OrderNet& net, std::vector<int32_t>& order, double& flops) {
 constexpr int kMaxOptimal = 12;
 
 // exact minimum over contraction trees of one connected component
-void optimal_component(const OrderNet& net, const std::vector<int>& comp, std::vector<int32_t>& order, double& flops) {
+int32_t optimal_component(const OrderNet& net, const std::vector<int>& comp, std::vector<int32_t>& order,
+                          double& flops) {
   const int n = (int)comp.size();
   const uint32_t full = (1u << n) - 1;
   std::vector<std::vector<int32_t>> lab(full + 1);
@@ -173,6 +207,8 @@ void optimal_component(const OrderNet& net, const std::vector<int>& comp, std::v
       const uint32_t b = s ^ a;
       if (cost[a] == INFINITY || cost[b] == INFINITY) continue;
       if (shared_label(lab[a], lab[b]) == INT32_MIN) continue;
+      // the merge's result must fit a tensor descriptor (the whole set's labels)
+      if ((int)lab[s].size() > TN_MAX_RANK) continue;
       const double c = cost[a] + cost[b] + pair_flops(net, lab[a], lab[b]);
       if (c < cost[s]) {
         cost[s] = c;
@@ -180,6 +216,8 @@ void optimal_component(const OrderNet& net, const std::vector<int>& comp, std::v
       }
     }
   }
+  if (n > 1 && cost[full] == INFINITY)
+    return fail(TN_ERR_UNSUPPORTED, "no contraction order keeps every intermediate within rank %d", TN_MAX_RANK);
   flops += cost[full];
   // post-order: contract both sides, then the merge
   std::vector<std::pair<uint32_t, bool>> stack = {{full, false}};
@@ -196,6 +234,7 @@ void optimal_component(const OrderNet& net, const std::vector<int>& comp, std::v
       stack.push_back({a, false});
     }
   }
+  return TN_OK;
 }
 
 }  // namespace
@@ -241,7 +280,7 @@ int32_t tn_network_order(int32_t n_nodes, const tn_tensor* nodes, const int32_t*
         if (comp_of[i] == c) comp.push_back((int)i);
       if ((int)comp.size() > kMaxOptimal)
         return fail(TN_ERR_UNSUPPORTED, "optimal order: a component has %zu nodes (at most %d)", comp.size(), kMaxOptimal);
-      optimal_component(net, comp, seq, f);
+      TN_TRY(optimal_component(net, comp, seq, f));
     }
   }
   // the driver contracts every shared label with the first one: list each

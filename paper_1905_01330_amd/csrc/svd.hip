@@ -386,23 +386,21 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
     W[(int64_t)colof(c) * R + (e - (int64_t)c * R)] = X[e];
   }
   __syncthreads();
-  // V[:, cols] <- V[:, cols] J, rows staged through the space X used
-  const int64_t chunk = (kLdsDoubles - NC * NC) / NC;
-  for (int64_t r0 = 0; r0 < Cp; r0 += chunk) {
-    const int64_t nr = Cp - r0 < chunk ? Cp - r0 : chunk;
-    for (int64_t e = tid; e < (int64_t)NC * nr; e += kNT) {
-      const int c = (int)(e / nr);
-      X[e] = V[(int64_t)colof(c) * Cp + r0 + (e - (int64_t)c * nr)];
-    }
-    __syncthreads();
-    for (int64_t e = tid; e < (int64_t)NC * nr; e += kNT) {
-      const int c = (int)(e / nr);
-      const int64_t r = e - (int64_t)c * nr;
+  // V[:, cols] <- V[:, cols] J: one row per thread at a time, the row's NC
+  // values in registers, J read from LDS (every lane reads the same entry)
+  for (int64_t r = tid; r < Cp; r += kNT) {
+    double v[NC], o[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = V[(int64_t)colof(c) * Cp + r];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
       double acc = 0.0;
-      for (int i = 0; i < NC; ++i) acc += X[(int64_t)i * nr + r] * J[i * NC + c];
-      V[(int64_t)colof(c) * Cp + r0 + r] = acc;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) acc += v[i] * J[i * NC + c];
+      o[c] = acc;
     }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) V[(int64_t)colof(c) * Cp + r] = o[c];
   }
 }
 
@@ -557,12 +555,23 @@ int32_t svd_geometry(const tn_tensor* a, int32_t n_left, SvdGeom& g) {
   g.R = std::max(g.ml, g.mr);
   g.C = std::min(g.ml, g.mr);
   if (g.C > 16384) return fail(TN_ERR_UNSUPPORTED, "the shorter effective leg (%lld) exceeds 16384", (long long)g.C);
+  // Block width: a sweep is nb - 1 rounds (nb ~ C / KB), each one launch
+  // whose pairs run side by side and whose work per pair grows like KB^2 R.
+  // Modelled sweep time: rounds x (5 us + 100 us x (KB / 8)^2 x R / 1000),
+  // measured for the pair kernel on gfx950; the cheapest width whose pair
+  // fits in LDS is taken.
   g.kb = kB;   // Gram-matrix pair kernel
-  for (int w : {8, 4, 2, 1})
-    if (g.R <= lds_rows(w)) {
+  double best = INFINITY;
+  for (int w : {8, 4, 2, 1}) {
+    if (g.R > lds_rows(w)) continue;
+    int nbw = (int)((g.C + w - 1) / w);
+    nbw = nbw < 2 ? 2 : nbw + (nbw % 2);
+    const double t = (nbw - 1) * (5.0 + 100.0 * (w / 8.0) * (w / 8.0) * (double)g.R / 1000.0);
+    if (t < best) {
+      best = t;
       g.kb = w;
-      break;
     }
+  }
   g.lds = g.R <= kMaxLdsRows;
   g.nb = (int)((g.C + g.kb - 1) / g.kb);
   if (g.nb < 2) g.nb = 2;

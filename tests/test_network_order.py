@@ -143,3 +143,29 @@ def test_order_errors():
         tn.network_order(ts, ring, "optimal")
     order, flops = tn.network_order(ts, ring, "greedy")
     assert sorted(order) == list(range(13)) and flops > 0
+
+
+@pytest.mark.parametrize("ops", [(), (5,), (7, 8), (0, 15)])
+def test_greedy_orders_of_mera_networks_fit_the_descriptor_rank(ops):
+    """The 16-site binary MERA's <psi|O|psi> networks have pairwise orders
+    whose intermediates keep at most 8 axes; the search must find one (the
+    driver's planning, host only, accepts it)."""
+    import ctypes as C
+
+    import torch
+
+    import paper_1905_01330_amd as tn
+    from paper_1905_01330_amd import _lib as L
+    from paper_1905_01330_amd import networks
+
+    shapes, labels, _ = networks.expectation(16, 2, 8, ops, True)
+    ts = [torch.empty(s) for s in shapes]
+    order, flops = tn.network_order(ts, labels, "greedy")
+    flat, offs = [], [0]
+    for lab in labels:
+        flat.extend(lab)
+        offs.append(len(flat))
+    nb = C.c_size_t(0)
+    assert L.lib().tn_contract_network_workspace(len(ts), L.tensor_array(ts), L.int_array(flat), L.int_array(offs),
+                                                 len(order), L.int_array(order), C.byref(nb)) == 0
+    assert flops < 1e9
