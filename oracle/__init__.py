@@ -36,3 +36,4 @@ from .classifier import (  # noqa: F401
 from .precision import bf16_round, split3, emulate_split_gemm  # noqa: F401
 from .split import split_node, split_node_full_svd, truncation_rank  # noqa: F401
 from .dmrg import heff_apply, heff_dense, two_site_update, dmrg  # noqa: F401
+from .complex import tensordot_c, mps_inner_c, mps_to_dense_c  # noqa: F401

@@ -175,3 +175,12 @@ def labels(batch: int, n_labels: int, seed) -> np.ndarray:
 def random_directions(shapes, seed) -> list[np.ndarray]:
     rng = np.random.default_rng(seed)
     return [rng.standard_normal(s) for s in shapes]
+
+
+def random_mps_complex(n_sites: int, d: int, chi: int, seed, dims=None) -> list[np.ndarray]:
+    """Complex sites: real and imaginary parts i.i.d. N(0,1)/sqrt(2 chi d)."""
+    rng = np.random.default_rng(seed)
+    dims = bond_dims(n_sites, d, chi) if dims is None else dims
+    scale = 1.0 / np.sqrt(2 * chi * d)
+    return [(rng.standard_normal((dims[k], d, dims[k + 1])) + 1j * rng.standard_normal((dims[k], d, dims[k + 1])))
+            * scale for k in range(n_sites)]
