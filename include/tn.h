@@ -22,7 +22,8 @@
  *    invalid call returns a negative tn_status and has no side effects;
  *    tn_last_error() then holds a one-line description (thread-local).
  *  - NaN and Inf propagate through arithmetic; they are not errors.
- *  - Real arithmetic only: conjugation is the identity.
+ *  - Real arithmetic unless a call says otherwise (the *_c64 calls take
+ *    complex tensors and conjugation flags).
  *  - Calls on different streams may run concurrently; calls that write the
  *    same workspace or output on overlapping streams race.
  */
@@ -38,7 +39,9 @@ extern "C" {
 
 #define TN_MAX_RANK 8
 
-typedef enum { TN_F32 = 0, TN_F64 = 1 } tn_dtype;
+/* TN_C64: complex, interleaved (real, imaginary) FP32 pairs; strides count
+ * complex elements. */
+typedef enum { TN_F32 = 0, TN_F64 = 1, TN_C64 = 2 } tn_dtype;
 
 /* Arithmetic used for the contracted-index products.
  *  FP32          FP32 operands, FP32 accumulation (matrix cores, fp32 MFMA).
@@ -105,6 +108,22 @@ const char* tn_version(void);
 int32_t tn_contract_between(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs,
                             const int32_t* axes_a, const int32_t* axes_b, tn_tensor* out,
                             void* workspace, size_t ws_bytes, int32_t prec, void* stream);
+
+/* Complex pairwise contraction (the V^dagger of III.B: complex nodes):
+ * out = op_a(a) . op_b(b) over the paired axes, op = complex conjugation
+ * when conj_a / conj_b is nonzero.  a, b, out: TN_C64 (a, out of rank <= 7,
+ * b of rank <= 6).  The right operand is expanded once into a real tensor
+ * holding (Re b, -Im b; Im b, Re b) with the conjugation signs folded in,
+ * in the workspace; one real contraction over (k, real/imaginary) then
+ * writes the interleaved complex result (four real products per complex
+ * product) on the real path, in precision `prec`.  workspace: at least
+ * tn_contract_between_c64_workspace(b) bytes.  Errors as
+ * tn_contract_between. */
+int32_t tn_contract_between_c64_workspace(const tn_tensor* b, size_t* bytes);
+int32_t tn_contract_between_c64(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs,
+                                const int32_t* axes_a, const int32_t* axes_b, int32_t conj_a,
+                                int32_t conj_b, tn_tensor* out, void* workspace, size_t ws_bytes,
+                                int32_t prec, void* stream);
 
 /* Trace edge (III.A "Trace Edges"; the trace of Fig. 2):
  * out[rest] = sum_i a[.. i .. i ..] over axis1 and axis2 (equal dims),
@@ -191,6 +210,17 @@ int32_t tn_mps_inner_workspace(int32_t n_sites, const tn_tensor* psi, const tn_t
                                size_t* bytes);
 int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi, double* out2,
                      void* workspace, size_t ws_bytes, int32_t prec, void* stream);
+
+/* Complex MPS inner product <psi|phi> = sum conj(psi(s)) phi(s): psi[k],
+ * phi[k] TN_C64 [D_k, d, D_{k+1}]; out4 (DEVICE, 4 doubles) = [Re m, Im m,
+ * s, 0] with value m * exp(s).  Each site is two complex contractions
+ * (E . phi_k, then conj(psi_k) over (a', s)) and an exact power-of-two
+ * rescale of E by its largest component.  Workspace from
+ * tn_mps_inner_c64_workspace. */
+int32_t tn_mps_inner_c64_workspace(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi,
+                                   size_t* bytes);
+int32_t tn_mps_inner_c64(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi, double* out4,
+                         void* workspace, size_t ws_bytes, int32_t prec, void* stream);
 
 /* Many independent inner products in one call (chains of uneven length and
  * bond dimension).  psi_sites/phi_sites hold all chains' sites back to back;

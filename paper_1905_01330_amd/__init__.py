@@ -19,6 +19,7 @@ from .api import (  # noqa: F401
     mps_env_sweep,
     mps_inner,
     mps_inner_batched,
+    mps_inner_complex,
     mps_left_canonicalize,
     network_order,
     outer_product,

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtn.so")
 MAX_RANK = 8
 
-F32, F64 = 0, 1
+F32, F64, C64 = 0, 1, 2
 PREC = {"fp32": 0, "bf16": 1, "split_bf16": 2, "split_bf16_3p": 3}
 
 STATUS = {
@@ -52,6 +52,10 @@ _PROTOS = {
     "tn_last_error": (C.c_char_p, []),
     "tn_version": (C.c_char_p, []),
     "tn_contract_between": (I32, [TP, TP, I32, I32P, I32P, TP, P, SZ, I32, P]),
+    "tn_contract_between_c64_workspace": (I32, [TP, C.POINTER(SZ)]),
+    "tn_contract_between_c64": (I32, [TP, TP, I32, I32P, I32P, I32, I32, TP, P, SZ, I32, P]),
+    "tn_mps_inner_c64_workspace": (I32, [I32, TP, TP, C.POINTER(SZ)]),
+    "tn_mps_inner_c64": (I32, [I32, TP, TP, P, P, SZ, I32, P]),
     "tn_trace_edge": (I32, [TP, I32, I32, TP, P]),
     "tn_outer_product": (I32, [TP, TP, TP, P]),
     "tn_contract_network_workspace": (I32, [I32, TP, I32P, I32P, I32, I32P, C.POINTER(SZ)]),
@@ -124,6 +128,8 @@ def tensor_desc(t, dtype=None) -> TnTensor:
             dtype = F32
         elif t.dtype == torch.float64:
             dtype = F64
+        elif t.dtype == torch.complex64:
+            dtype = C64
         else:
             raise TypeError(f"unsupported dtype {t.dtype}")
     d.dtype = dtype

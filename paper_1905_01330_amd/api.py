@@ -23,13 +23,19 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def contract_between(a, b, axes_a, axes_b, out=None, prec="fp32"):
+def contract_between(a, b, axes_a, axes_b, out=None, prec="fp32", conj_a=False, conj_b=False):
     """Contract axes_a[i] of a with axes_b[i] of b (section III.B, flattened edges).
 
     Output axes: free axes of a (ascending) then free axes of b.  `out` may be
     any strided view of that shape (a permuted view fuses reorder_edges).
+    Complex (complex64) operands take the complex path, with optional
+    conjugation of either operand.
     """
     _dev(a), _dev(b)
+    if a.is_complex() or b.is_complex():
+        return _contract_c64(a, b, axes_a, axes_b, out, prec, conj_a, conj_b)
+    if conj_a or conj_b:
+        raise ValueError("conjugation applies to complex operands")
     axes_a = [int(x) % max(a.dim(), 1) for x in axes_a]
     axes_b = [int(x) % max(b.dim(), 1) for x in axes_b]
     if out is None:
@@ -44,6 +50,41 @@ def contract_between(a, b, axes_a, axes_b, out=None, prec="fp32"):
                                         C.c_void_p(ws.data_ptr()) if ws is not None else None,
                                         ws.numel() if ws is not None else 0, L.prec_code(prec), L.stream_ptr()))
     return out
+
+
+def _contract_c64(a, b, axes_a, axes_b, out, prec, conj_a, conj_b):
+    if a.dtype != torch.complex64 or b.dtype != torch.complex64:
+        raise TypeError("complex contractions take complex64 operands")
+    axes_a = [int(x) % max(a.dim(), 1) for x in axes_a]
+    axes_b = [int(x) % max(b.dim(), 1) for x in axes_b]
+    if out is None:
+        shape = [a.shape[i] for i in range(a.dim()) if i not in axes_a] + \
+                [b.shape[j] for j in range(b.dim()) if j not in axes_b]
+        out = torch.empty(shape, dtype=torch.complex64, device=a.device)
+    da, db, do = L.tensor_desc(a), L.tensor_desc(b), L.tensor_desc(out)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_contract_between_c64_workspace(C.byref(db), C.byref(nbytes)))
+    ws = _workspace(nbytes.value, a.device)
+    L.check(L.lib().tn_contract_between_c64(C.byref(da), C.byref(db), len(axes_a), L.int_array(axes_a),
+                                            L.int_array(axes_b), int(bool(conj_a)), int(bool(conj_b)), C.byref(do),
+                                            C.c_void_p(ws.data_ptr()), nbytes.value, L.prec_code(prec),
+                                            L.stream_ptr()))
+    return out
+
+
+def mps_inner_complex(psi, phi, prec="fp32"):
+    """<psi|phi> for complex64 chains as a device float64 tensor [Re m, Im m, s]
+    with value m * exp(s) (psi's sites are conjugated)."""
+    n = len(psi)
+    dp, dq = L.tensor_array(psi), L.tensor_array(phi)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_mps_inner_c64_workspace(n, dp, dq, C.byref(nbytes)))
+    dev = psi[0].device
+    ws = _workspace(nbytes.value, dev)
+    out4 = torch.empty(4, dtype=torch.float64, device=dev)
+    L.check(L.lib().tn_mps_inner_c64(n, dp, dq, C.c_void_p(out4.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                     nbytes.value, L.prec_code(prec), L.stream_ptr()))
+    return out4[:3]
 
 
 def tensordot(a, b, axes_a, axes_b, prec="fp32"):

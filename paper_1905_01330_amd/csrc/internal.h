@@ -82,6 +82,12 @@ int32_t side_stream(hipStream_t& out);
 int forced_grouped_cfg();
 int grouped_tile_n(int cfg);
 
+// ---- complex contraction on the real path (complex.hip) -----------------------
+size_t c64_workspace_bytes(const tn_tensor& b);
+int32_t contract_c64_impl(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs, const int32_t* axes_a,
+                          const int32_t* axes_b, int conj_a, int conj_b, tn_tensor* out, void* workspace,
+                          size_t ws_bytes, int32_t prec, hipStream_t st);
+
 // ---- contraction entry used by the network driver -----------------------------
 int32_t contract_between_impl(const tn_tensor* a, const tn_tensor* b, int32_t n_pairs, const int32_t* axes_a,
                               const int32_t* axes_b, tn_tensor* out, void* scratch, size_t scratch_bytes,

@@ -40,7 +40,8 @@ int32_t check_tensor(const tn_tensor* t, const char* name, int32_t dtype) {
   if (t->rank < 0 || t->rank > TN_MAX_RANK) return fail(TN_ERR_INVALID_ARGUMENT, "%s: rank %d out of range", name, t->rank);
   if (dtype >= 0 && t->dtype != dtype)
     return fail(TN_ERR_UNSUPPORTED, "%s: dtype %d not supported here (want %d)", name, t->dtype, dtype);
-  if (t->dtype != TN_F32 && t->dtype != TN_F64) return fail(TN_ERR_UNSUPPORTED, "%s: unknown dtype %d", name, t->dtype);
+  if (t->dtype != TN_F32 && t->dtype != TN_F64 && t->dtype != TN_C64)
+    return fail(TN_ERR_UNSUPPORTED, "%s: unknown dtype %d", name, t->dtype);
   if (!t->data) return fail(TN_ERR_INVALID_ARGUMENT, "%s: data is NULL", name);
   for (int i = 0; i < t->rank; ++i) {
     if (t->shape[i] < 1) return fail(TN_ERR_INVALID_ARGUMENT, "%s: shape[%d] = %lld < 1", name, i, (long long)t->shape[i]);
@@ -59,7 +60,7 @@ int64_t numel(const tn_tensor& t) {
 void byte_extent(const tn_tensor& t, uintptr_t& lo, uintptr_t& hi) {
   int64_t last = 0;
   for (int i = 0; i < t.rank; ++i) last += (t.shape[i] - 1) * t.stride[i];
-  const int64_t es = t.dtype == TN_F64 ? 8 : 4;
+  const int64_t es = (t.dtype == TN_F64 || t.dtype == TN_C64) ? 8 : 4;
   lo = reinterpret_cast<uintptr_t>(t.data);
   hi = lo + (uintptr_t)((last + 1) * es);
 }

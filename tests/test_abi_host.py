@@ -279,3 +279,22 @@ def test_dmrg_validation_and_workspace_on_host():
     bad = desc([8, 2, 2, 7], B0)
     assert lib.tn_dmrg_workspace(C.byref(Lt), C.byref(Rt), C.byref(w1), C.byref(w2), C.byref(bad), 24,
                                  C.byref(nbytes)) == -2
+
+
+def test_complex_validation_before_launch():
+    lib = L.lib()
+    a = desc([4, 5], A0, dtype=L.C64)
+    b = desc([5, 6], B0, dtype=L.C64)
+    out = desc([4, 6], O0, dtype=L.C64)
+    nbytes = C.c_size_t(0)
+    assert lib.tn_contract_between_c64_workspace(C.byref(b), C.byref(nbytes)) == 0 and nbytes.value >= 16 * 30
+    call = lambda x, y, o, pa, pb: lib.tn_contract_between_c64(C.byref(x), C.byref(y), len(pa), L.int_array(pa),
+                                                              L.int_array(pb), 1, 0, C.byref(o), FAKE + (5 << 30),
+                                                              nbytes.value, 0, None)
+    assert call(a, b, desc([4, 6], O0), [1], [0]) == -3                 # real out
+    assert call(a, desc([6, 6], B0, dtype=L.C64), out, [1], [0]) == -2  # 5 vs 6
+    assert call(a, b, out, [2], [0]) == -1
+    assert lib.tn_contract_between_c64(C.byref(a), C.byref(b), 1, L.int_array([1]), L.int_array([0]), 0, 0,
+                                       C.byref(out), FAKE + (5 << 30), 16, 0, None) == -4
+    big = desc([2] * 7, B0, dtype=L.C64)                                 # b of rank 7: above 6
+    assert lib.tn_contract_between_c64_workspace(C.byref(big), C.byref(nbytes)) == -3
