@@ -49,11 +49,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "next", "batched", "canonicalize"],
+    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "next", "batched", "canonicalize", "profile"],
                     default="sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--chains", type=int, default=512, help="--mode batched: first N chains of the uneven batch")
-    ap.add_argument("--prec", default="fp32", help="--mode batched: precision")
+    ap.add_argument("--prec", default="fp32", help="--mode batched and profile: precision")
+    ap.add_argument("--max-chi", type=int, default=0, help="--mode batched: only chains with chi <= this (0: all)")
+    ap.add_argument("--workload", choices=["chi1024", "chi256"], default="chi1024",
+                    help="--mode profile: the XXZ N=64 chi=1024 sweep or the TFIM N=100 chi=256 sweep")
+    ap.add_argument("--direction", choices=["left", "right", "both"], default="both", help="--mode profile")
     return ap.parse_args()
 
 
@@ -116,6 +120,17 @@ def load_uneven_batch(torch, inputs, shapes):
             chains.append((psi, phi))
     torch.cuda.synchronize()
     return chains, bufs
+
+
+def copy_calibration(torch):
+    """A plain 256 MiB device copy, three times: the reference kernel that
+    calibrates the HBM byte counters of a profiled run."""
+    src = torch.ones(64 << 20, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 2 * src.numel() * 4
 
 
 def time_loop(torch, fn, steps, warmup):
@@ -642,10 +657,29 @@ def main():
         shapes = inputs.uneven_chain_shapes()
         if a.chains < len(shapes):
             shapes = shapes[:a.chains]
+        if a.max_chi:
+            shapes = [s for s in shapes if s[1] <= a.max_chi]
         chains, keep = load_uneven_batch(torch, inputs, shapes)
         bi = tn.BatchedInner(chains, a.prec)
         ms = time_loop(torch, bi.run, a.steps, a.warmup)
-        print(json.dumps({"mode": "batched", "chains": len(shapes), "precision": a.prec, "ms_per_call": round(ms, 4)}))
+        del bi, chains, keep
+        print(json.dumps({"mode": "batched", "chains": len(shapes), "precision": a.prec, "ms_per_call": round(ms, 4),
+                          "copy_bytes": copy_calibration(torch)}))
+        return
+    if a.mode == "profile":
+        # one sweep configuration in one or both directions, for kernel traces
+        # and HBM counters of its kernels alone
+        tn.tune_set_level(1)
+        if a.workload == "chi1024":
+            psi, mpo = gpu_inputs(torch, tn, inputs)
+        else:
+            psi, mpo = gpu_inputs(torch, tn, inputs, n_sites=100, chi=256, seed=201, model="tfim")
+        sw = tn.EnvSweep(psi, mpo, left=a.direction != "right", right=a.direction != "left", store=True,
+                         prec=a.prec)
+        ms = time_loop(torch, sw.run, a.steps, a.warmup)
+        del sw, psi, mpo
+        print(json.dumps({"mode": "profile", "workload": a.workload, "direction": a.direction, "precision": a.prec,
+                          "ms_per_call": round(ms, 4), "copy_bytes": copy_calibration(torch)}))
         return
     if a.mode == "canonicalize":
         dev = torch.device("cuda:0")
@@ -665,14 +699,7 @@ def main():
     if a.mode == "tensordot":
         tn.tune_set_level(1)
         flops, res, _ = headline(torch, tn, a.steps, a.warmup, graph=False)
-        # a plain 256 MiB device copy in the same process: the reference
-        # kernel that calibrates the HBM byte counters
-        src = torch.ones(64 << 20, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"mode": "tensordot", "flops": flops, "copy_bytes": 2 * src.numel() * 4, **res}))
+        print(json.dumps({"mode": "tensordot", "flops": flops, "copy_bytes": copy_calibration(torch), **res}))
         return
 
     tn.tune_set_level(1)   # time the tile candidates once per contraction shape (during warm-up)
