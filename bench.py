@@ -294,6 +294,7 @@ def _row(rid, what, workload, work, ms, kind, cpu_work, cpu_s, sample, extra=Non
     peak, unit = PEAK_ROWS[kind]
     scale = 1e9 if unit == "GB/s" else 1e12
     val = work / (ms * 1e-3) / scale
+    print(f"row {rid} done: {ms:.4f} ms", file=sys.stderr, flush=True)
     r = {"row": rid, "what": what, "workload": workload, "ms": round(ms, 4),
          "roofline": {"bound": "hbm" if kind == "hbm" else "mfma", "achieved": round(val, 3), "peak": peak,
                       "unit": unit, "frac": round(val / peak, 4)},
@@ -329,18 +330,20 @@ def rows(torch, tn, inputs):
     for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
         ms1 = _gtime(torch, tn, lambda: tn.contract_between(L, A, [2], [0], out=o1, prec=prec), reps=HEAD_REPS,
                      steps=5, warmup=2)
+        tile1 = tn.tune_last_choice()
         ms3 = _gtime(torch, tn, lambda: tn.contract_between(T2, A, [0, 1], [0, 1], out=o3, prec=prec),
                      reps=HEAD_REPS, steps=5, warmup=2)
+        tile3 = tn.tune_last_choice()
         c1 = _ctime(lambda: oracle.contract_between(Lh[:64], Ah, [(2, 0)]))
         c3 = _ctime(lambda: oracle.contract_between(T2h, Ah[:, :, :64], [(0, 0), (1, 1)]))
         w1 = "L[1024,5,1024] . A[1024,2,1024] over (2,0): M=5120 K=1024 N=2048"
         w3 = "T2[1024,2,5,1024] . A[1024,2,1024] over ((0,1),(0,1)), stored permuted into L[1024,5,1024]"
-        extra = {"precision": prec}
+        extra = {"precision": prec, "tile_config": tile1}
         if prec == "split_bf16":
             extra["issued_mfma_frac"] = round(6 * fl / (ms1 * 1e-3) / 1e12 / PEAK["bf16"], 4)
         out.append(_row("a1-a4 T1", "tensordot (plan, fused gather, GEMM, epilogue)", w1, fl, ms1, kind,
                         2.0 * 64 * 5 * 1024 * 2048, c1, "first 64 rows of L", extra))
-        extra = {"precision": prec}
+        extra = {"precision": prec, "tile_config": tile3}
         out.append(_row("a1-a4 T3", "tensordot with a permuted output", w3, fl, ms3, kind,
                         2.0 * 64 * 2048 * 5120, c3, "first 64 columns of A", extra))
     del L, A, T2, o1, Lout, Lh, Ah, T2h
@@ -568,6 +571,22 @@ def next_rows(torch, tn, inputs):
     out.append(_row("n1", "split_node, FP64 one-sided block Jacobi SVD + truncation", "1000 x 1000 node, "
                     "max_singular_values=5 (Appendix A example)", svd_flops, ms, "fp64", svd_flops, c,
                     "the same node (numpy LAPACK SVD)", {"note": "host-timed; synchronising call"}))
+
+    # complex contraction at the bulk-site shape: L[1024,5,1024] . conj(A[1024,2,1024]) over (2,0)
+    lc = (rng.standard_normal((1024, 5, 1024)) + 1j * rng.standard_normal((1024, 5, 1024))).astype(np.complex64)
+    ac = ((rng.standard_normal((1024, 2, 1024)) + 1j * rng.standard_normal((1024, 2, 1024))) /
+          np.sqrt(4096)).astype(np.complex64)
+    glc, gac = torch.tensor(lc, device=dev), torch.tensor(ac, device=dev)
+    cfl = 8.0 * 5120 * 2048 * 1024          # four real products and four additions per complex term
+    lch = lc[:64].astype(np.complex128)
+    ach = ac.astype(np.complex128)
+    cc = _ctime(lambda: oracle.tensordot_c(lch, ach, [2], [0], False, True))
+    for prec, kind in (("split_bf16", "bf16"), ("fp32", "fp32")):
+        ms = _gtime(torch, tn, lambda: tn.contract_between(glc, gac, [2], [0], prec=prec, conj_b=True), reps=5)
+        out.append(_row("n2", "complex tensordot, conjugated right operand (expansion + one real contraction)",
+                        "L[1024,5,1024] . conj(A[1024,2,1024]) over (2,0), complex64", cfl, ms, kind,
+                        cfl * 64 / 1024, cc, "first 64 rows of L (complex FP64)", {"precision": prec}))
+    del glc, gac, lc, ac, lch, ach
 
     # one two-site DMRG update at chi = 256 (TFIM, bulk sites of the N = 100 chain)
     psi, mpo = gpu_inputs(torch, tn, inputs, n_sites=100, chi=256, seed=201, model="tfim")
