@@ -19,8 +19,11 @@ namespace tn {
 
 struct Cfg {
   int bm, bn, bk, wm, wn;
-  float eff;   // relative per-tile efficiency used by the heuristic
-  int wk = 1;  // k-slice groups of wm x wn waves
+  float eff;          // relative per-tile efficiency used by the heuristic
+  int wk = 1;         // k-slice groups of wm x wn waves
+  int split = 0;      // lean-stage split-BF16 kernel kind (gemm_split.hip), 0: general kernel
+  int fallback = -1;  // general configuration of the same tile shape, for problems the kind cannot take
+  bool swap = false;  // run on the transposed problem C^T = B^T A^T (operands exchanged)
 };
 
 // eff: relative per-tile throughput measured on the bulk environment-sweep
@@ -32,6 +35,13 @@ static const Cfg kCfgs[] = {
     {128, 160, 16, 4, 1, 1.00f},   {160, 256, 32, 1, 8, 2.00f}, {256, 160, 32, 8, 1, 2.00f},
     {128, 160, 32, 4, 1, 1.60f, 2}, {160, 128, 32, 1, 4, 1.60f, 2}, {64, 64, 64, 2, 2, 0.45f, 2},
     {64, 64, 64, 2, 2, 0.55f},
+    // lean-stage split-BF16 kernels (split-BF16 precision, k-contiguous A,
+    // B along k or n, K % 8 == 0, 31-bit byte offsets); tiles as 10 and 13
+    {160, 256, 32, 1, 8, 2.30f, 1, 1, 10}, {160, 256, 32, 1, 8, 2.20f, 1, 2, 10},
+    {160, 128, 32, 1, 4, 1.75f, 2, 3, 13},
+    // the same on the exchanged operands (B k-contiguous); tiles as 11 and 12
+    {256, 160, 32, 8, 1, 2.30f, 1, 1, 11, true}, {256, 160, 32, 8, 1, 2.20f, 1, 2, 11, true},
+    {128, 160, 32, 4, 1, 1.75f, 2, 3, 12, true},
 };
 static constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -45,7 +55,52 @@ static int gemm_variant(const GemmDesc& d) {
   return 1 + (d.a_mode == LOAD_MNVEC ? 2 : 0) + (d.b_mode == LOAD_MNVEC ? 1 : 0);
 }
 
-static GemmFn pick_fn(const GemmDesc& d, int prec, int cfg) { return gemm_fn_prec(prec, cfg, gemm_variant(d)); }
+// the lean-stage split-BF16 kernels take the split precision with one
+// merged contracted axis, A read along it in 16-byte loads, K a multiple of 8
+// (whole 8-k runs) and every element of one batch entry within a 31-bit byte
+// offset of the view's base (buffer loads).  B is read in 16-byte loads when
+// it is k-contiguous, else one element per lane along k (lanes along n).
+static bool split_ok(const GemmDesc& d, int prec) {
+  if (prec != TN_PREC_SPLIT_BF16 || d.gk.n != 1 || d.a_mode != LOAD_KVEC || d.K % 8 != 0) return false;
+  auto extent = [](const Group& g, int t) {
+    int64_t e = 0;
+    for (int i = 0; i < g.n; ++i) e += (int64_t)(g.dim[i] - 1) * g.s[t][i];
+    return e;
+  };
+  const int64_t ea = extent(d.gm, 0) + extent(d.gk, 0) + 8;
+  const int64_t eb = extent(d.gn, 0) + extent(d.gk, 1) + 8;
+  return ea * 4 < (1ll << 31) && eb * 4 < (1ll << 31);
+}
+
+// C^T = B^T A^T: the operands and the M and N groups exchanged (the output
+// strides travel with their groups), modes re-derived
+static GemmDesc exchanged(const GemmDesc& d) {
+  GemmDesc e = d;
+  e.a = d.b;
+  e.b = d.a;
+  e.M = d.N;
+  e.N = d.M;
+  e.a_bs = d.b_bs;
+  e.b_bs = d.a_bs;
+  e.gm = d.gn;
+  e.gn = d.gm;
+  for (int i = 0; i < kMaxAxes; ++i) {
+    e.gk.s[0][i] = d.gk.s[1][i];
+    e.gk.s[1][i] = d.gk.s[0][i];
+  }
+  choose_modes(e);
+  return e;
+}
+
+// lean: run the lean kind of cfg (the caller has checked that it applies to d)
+static GemmFn pick_fn(const GemmDesc& d, int prec, int cfg, bool lean) {
+  const Cfg& g = kCfgs[cfg];
+  if (g.split) {
+    if (lean) return split_fn(g.split, d.b_mode == LOAD_KVEC ? LOAD_KVEC : LOAD_MNVEC);
+    cfg = g.fallback;
+  }
+  return gemm_fn_prec(prec, cfg, gemm_variant(d));
+}
 
 // grouped configurations: 0 -> 128x128, 1 -> 64x64, 2 -> 32x32, 3 -> 64x64 in two k-slices
 static const int kGroupedCfg[4] = {3, 15, 7, 14};
@@ -61,21 +116,23 @@ int forced_grouped_cfg() { return g_forced_grouped.load(); }
 
 // eight-wave tiles larger than 64 x 64 have a fixed 256-register budget that
 // the run-time-mode gathers exceed: they serve the fast gathers only
-static bool cfg_allowed(const GemmDesc& d, int c) {
+// (the lean-stage kinds only where they apply)
+static bool cfg_allowed(const GemmDesc& d, int prec, int c) {
   const Cfg& g = kCfgs[c];
+  if (g.split) return split_ok(g.swap ? exchanged(d) : d, prec);
   return g.wm * g.wn * g.wk < 8 || g.bm * g.bn <= 64 * 64 || gemm_variant(d) != 0;
 }
 
-static int heuristic_cfg(const GemmDesc& d) {
+static int heuristic_cfg(const GemmDesc& d, int prec) {
   const int forced = g_forced_cfg.load();
   if (forced >= 0) return forced;
   constexpr int kSlots = 256;  // one workgroup per compute unit for the large tiles
   double best = 1e300;
   int best_c = 7;   // 32 x 32 tiles fit every problem
   for (int c = 0; c < kNumCfgs; ++c) {
-    if (!cfg_allowed(d, c)) continue;
+    if (!cfg_allowed(d, prec, c)) continue;
     const Cfg& g = kCfgs[c];
-    const int64_t tiles = (int64_t)((d.M + g.bm - 1) / g.bm) * ((d.N + g.bn - 1) / g.bn) * d.batch;
+    const int64_t tiles = (int64_t)((d.M + g.bm - 1) / g.bm) * ((d.N + g.bn - 1) / g.bn) * d.batch;  // bm x bn as the caller's M x N
     const int64_t rounds = (tiles + kSlots - 1) / kSlots;
     // rounds of full-chip occupancy times the work of one tile over its efficiency
     const double est = (double)rounds * g.bm * g.bn / g.eff;
@@ -153,28 +210,46 @@ bool log_enabled() {
 int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st) {
   if (cfg < 0 || cfg >= kNumCfgs) return fail(TN_ERR_INVALID_ARGUMENT, "bad tile config %d", cfg);
   const Cfg& g = kCfgs[cfg];
-  d.tiles_m = (d.M + g.bm - 1) / g.bm;
-  d.tiles_n = (d.N + g.bn - 1) / g.bn;
-  const int64_t tiles = (int64_t)d.tiles_m * d.tiles_n;
-  if (tiles >= (1ll << 31) || d.batch > 65535) return fail(TN_ERR_UNSUPPORTED, "grid too large");
-  hipLaunchKernelGGL(pick_fn(d, prec, cfg), dim3((unsigned)tiles, 1, (unsigned)d.batch), dim3(g.wm * g.wn * g.wk * 64), 0,
-                     st, d);
+  // the problem the kernel runs on (exchanged operands for the swap kinds)
+  // and whether the lean kind applies; otherwise the general tile of the
+  // same shape runs on the caller's problem
+  GemmDesc x = d;
+  bool lean = false;
+  if (g.split) {
+    if (g.swap) {
+      GemmDesc e = exchanged(d);
+      if (split_ok(e, prec)) {
+        x = e;
+        lean = true;
+      }
+    } else {
+      lean = split_ok(d, prec);
+    }
+  }
+  const Cfg& t = (g.split && !lean) ? kCfgs[g.fallback] : g;
+  const int bm = (lean && g.swap) ? t.bn : t.bm, bn = (lean && g.swap) ? t.bm : t.bn;
+  x.tiles_m = (x.M + bm - 1) / bm;
+  x.tiles_n = (x.N + bn - 1) / bn;
+  const int64_t tiles = (int64_t)x.tiles_m * x.tiles_n;
+  if (tiles >= (1ll << 31) || x.batch > 65535) return fail(TN_ERR_UNSUPPORTED, "grid too large");
+  hipLaunchKernelGGL(pick_fn(x, prec, cfg, lean), dim3((unsigned)tiles, 1, (unsigned)x.batch),
+                     dim3(t.wm * t.wn * t.wk * 64), 0, st, x);
   return hip_check(hipGetLastError(), "gemm launch");
 }
 
 static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return heuristic_cfg(d);
+  if (hipEventCreate(&e0) != hipSuccess) return heuristic_cfg(d, prec);
   if (hipEventCreate(&e1) != hipSuccess) {
     hipEventDestroy(e0);
-    return heuristic_cfg(d);
+    return heuristic_cfg(d, prec);
   }
-  int best = heuristic_cfg(d);
+  int best = heuristic_cfg(d, prec);
   float best_ms = 1e30f;
   for (int c = 0; c < kNumCfgs; ++c) {
     const Cfg& g = kCfgs[c];
     if ((int64_t)g.bm * g.bn > 4ll * d.M * d.N && c != 7) continue;  // mostly padding (32 x 32 always runs)
-    if (!cfg_allowed(d, c)) continue;
+    if (!cfg_allowed(d, prec, c)) continue;
     if (launch_gemm_cfg(d, prec, c, st) != TN_OK) continue;  // warm-up
     hipEventRecord(e0, st);
     const int reps = level >= 2 ? 10 : 3;
@@ -224,10 +299,10 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
         cfg = tune_cfg(d, prec, level, st);
         timed = true;
       } else {
-        cfg = heuristic_cfg(d);
+        cfg = heuristic_cfg(d, prec);
       }
     } else {
-      cfg = heuristic_cfg(d);
+      cfg = heuristic_cfg(d, prec);
     }
     how = timed ? "timed" : "heuristic";
     std::lock_guard<std::mutex> lk(g_tune_mu);

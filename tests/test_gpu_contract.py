@@ -159,6 +159,47 @@ def test_ragged_gemm_all_tiles(prec):
         tn.tune_force_config(-1)
 
 
+# the last six tile configurations are the lean-stage split-BF16 kernels
+# (both operands through LDS; B private per wave; B private in two k
+# groups), then the same three on the exchanged operands
+LEAN_CFGS = [16, 17, 18, 19, 20, 21]
+
+
+@pytest.mark.parametrize("layout", ["kn", "kk", "mk"])
+@pytest.mark.parametrize("shape", [(197, 296, 259), (160, 32, 256), (5, 8, 7), (330, 1000, 520), (161, 64, 33)])
+def test_lean_split_kernels(shape, layout):
+    """Every lean-stage kernel, forced, on ragged tiles, a partial last k
+    stage, A along k or along m, B along n or along k, a two-axis M group and
+    a permuted output, against the oracle at the split-BF16 target.  Where a
+    lean kernel does not take the problem (precision, layout) the general
+    tile of the same shape runs."""
+    assert tn.tune_num_configs() == 22
+    M, K, N = shape
+    rng = np.random.default_rng(M * 7 + K)
+    m1 = 3 if M % 3 == 0 else 1
+    a = f32(rng.standard_normal((M // m1, m1, K)))
+    b = f32(rng.standard_normal((K, N)))
+    if layout[0] == "k":   # M group of two axes in reverse memory order, k contiguous
+        ga = gpu(a.transpose(1, 0, 2).copy()).permute(1, 0, 2)
+    else:                  # m contiguous
+        ga = gpu(a.transpose(2, 0, 1).copy()).permute(1, 2, 0)
+    gb = gpu(b) if layout[1] == "n" else gpu(b.T.copy()).t()
+    ref = oracle.tensordot(a, b, [2], [0])
+    scale = abs_scale(a, b, [2], [0])
+    try:
+        for cfg in LEAN_CFGS:
+            tn.tune_force_config(cfg)
+            out = tn.contract_between(ga, gb, [2], [0], prec="split_bf16")
+            check(host(out), ref, scale, TOL["split_bf16"], f"lean config {cfg}")
+            outp = torch.empty((N, M // m1, m1), device=DEV)
+            tn.contract_between(ga, gb, [2], [0], out=outp.permute(1, 2, 0), prec="split_bf16")
+            check(host(outp.permute(1, 2, 0)), ref, scale, TOL["split_bf16"], f"lean config {cfg}, permuted output")
+            out = tn.contract_between(ga, gb, [2], [0], prec="fp32")
+            check(host(out), ref, scale, TOL["fp32"], f"lean config {cfg} in FP32 (general tile)")
+    finally:
+        tn.tune_force_config(-1)
+
+
 @pytest.mark.parametrize("layout", ["kk", "mk", "km", "mm", "gen"])
 @pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
 def test_operand_layouts(layout, prec):
