@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--chains", type=int, default=512, help="--mode batched: first N chains of the uneven batch")
     ap.add_argument("--prec", default="fp32", help="--mode batched and profile: precision")
     ap.add_argument("--max-chi", type=int, default=0, help="--mode batched: only chains with chi <= this (0: all)")
+    ap.add_argument("--tune", type=int, default=1, choices=[0, 1, 2],
+                    help="--mode batched: tile autotuner level (0: the work estimate picks each step's tile)")
     ap.add_argument("--workload", choices=["chi1024", "chi256"], default="chi1024",
                     help="--mode profile: the XXZ N=64 chi=1024 sweep or the TFIM N=100 chi=256 sweep")
     ap.add_argument("--direction", choices=["left", "right", "both"], default="both", help="--mode profile")
@@ -679,11 +681,15 @@ def main():
         if a.max_chi:
             shapes = [s for s in shapes if s[1] <= a.max_chi]
         chains, keep = load_uneven_batch(torch, inputs, shapes)
+        if a.tune == 2:
+            tn.tune(None, 2)
+        else:
+            tn.tune_set_level(a.tune)
         bi = tn.BatchedInner(chains, a.prec)
-        ms = time_loop(torch, bi.run, a.steps, a.warmup)
+        ms = time_loop(torch, bi.run, a.steps, a.warmup)   # the first warm-up call times the step tiles
         del bi, chains, keep
-        print(json.dumps({"mode": "batched", "chains": len(shapes), "precision": a.prec, "ms_per_call": round(ms, 4),
-                          "copy_bytes": copy_calibration(torch)}))
+        print(json.dumps({"mode": "batched", "chains": len(shapes), "precision": a.prec, "tune": a.tune,
+                          "ms_per_call": round(ms, 4), "copy_bytes": copy_calibration(torch)}))
         return
     if a.mode == "profile":
         # one sweep configuration in one or both directions, for kernel traces

@@ -229,7 +229,10 @@ int32_t tn_mps_inner_c64(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
  * of 4 or more sites are contracted from both ends at once; all chains
  * advance together, one site per step and end, as grouped GEMMs over every
  * half still active, and each chain's halves meet in an FP64 sum over its
- * middle bond. */
+ * middle bond.  Each step's grouped tile comes from the tile autotuner
+ * (tn_tune: timed on the first launch per step signature and precision
+ * when tuning is on and the stream is not capturing), else from a work
+ * estimate. */
 int32_t tn_mps_inner_batched_workspace(int32_t n_chains, const int32_t* site_offsets,
                                        const tn_tensor* psi_sites, const tn_tensor* phi_sites,
                                        size_t* bytes);
@@ -240,9 +243,10 @@ int32_t tn_mps_inner_batched(int32_t n_chains, const int32_t* site_offsets,
  * HIP graph and replayed.  _upload writes the work tables (chain records,
  * grouped-GEMM problems) into the workspace and waits for the copy to
  * finish on `stream` (not capturable).  _launch only launches kernels on
- * `stream` (capturable); it uses the tables of the last _upload into the
- * same workspace, which must have been made with the same chains, tensors
- * and workspace.  Errors as tn_mps_inner_batched. */
+ * `stream` (capturable; while capturing it takes cached or estimated tiles
+ * and times nothing); it uses the tables of the last _upload into the same
+ * workspace, which must have been made with the same chains, tensors and
+ * workspace.  Errors as tn_mps_inner_batched. */
 int32_t tn_mps_inner_batched_upload(int32_t n_chains, const int32_t* site_offsets,
                                     const tn_tensor* psi_sites, const tn_tensor* phi_sites,
                                     void* workspace, size_t ws_bytes, void* stream);
@@ -410,14 +414,19 @@ int32_t tn_dmrg_eigensolve(const tn_tensor* L, const tn_tensor* R, const tn_tens
  *       1: on the first contraction of each new (shape, layout, precision)
  *          signature, time every candidate tile 3 times and keep the fastest;
  *       2: the same with 10 timed launches per candidate (less noise).
+ * The uneven batched inner product is tuned the same way per site step:
+ * the first launch of each (step signature, precision) times its four
+ * grouped tiles, re-running the step on its real inputs, and keeps the
+ * fastest.
  * Tile choices are cached per process; the cache is mutex-guarded, so
  * concurrent calls from several threads are safe.  Timing is skipped while
  * the stream is being captured into a graph (the heuristic is used then).
  *
  * tn_tune(cache_path, level): sets the level and, when cache_path is not
  * NULL, persists the choices in that text file: entries already in it are
- * loaded now (lines "M N K batch amode bmode cmode prec groups -> cfg",
- * malformed lines are skipped) and every choice made later is appended.
+ * loaded now (lines "M N K batch amode bmode cmode prec groups -> cfg" and
+ * "G step-signature prec -> grouped tile", malformed lines are skipped) and
+ * every timed choice made later is appended.
  * NULL keeps the choices in memory only.  Changing the level clears the
  * in-memory choices (the file is reloaded).  The environment variables
  * TN_TUNE=off|quick|full and TN_TUNE_CACHE=<path> give the starting state
@@ -439,10 +448,9 @@ int32_t tn_tune_force_config(int32_t cfg);
 int32_t tn_tune_num_configs(void);
 /* Pin the tile of every site step of the uneven batched inner product:
  * 0: 128 x 128, 1: 64 x 64, 2: 32 x 32, 3: 64 x 64 in two k-slices; -1
- * restores the per-step choice.  The tile tables are written by
- * tn_mps_inner_batched_upload, so the setting must not change between an
- * upload and the launches that use it (a launch with another setting stays
- * in bounds but computes wrong values).  Meant for measurement and tests.
+ * restores the per-step choice (tuned or estimated).  The upload writes the
+ * tile tables of all four tiles, so the setting may change between an
+ * upload and its launches.  Meant for measurement and tests.
  * TN_ERR_INVALID_ARGUMENT outside -1 .. 3. */
 int32_t tn_tune_force_grouped_config(int32_t cfg);
 

@@ -89,13 +89,16 @@ __global__ void __launch_bounds__(kFinishThreads) batched_finish_kernel(const Ch
 
 namespace {
 
+constexpr int kGroupedCfgs = 4;
+
 struct Launch {
-  size_t prob_off;   // index into the problem table
+  size_t prob_off;                   // index into the problem table
   int32_t n_probs;
-  size_t tile_off;   // index into the tile-start table
-  int32_t tiles;
-  int cfg;
-  int variant;   // gather variant shared by every problem of the launch
+  size_t tile_off[kGroupedCfgs];     // per grouped tile: index into the tile-start table
+  int32_t tiles[kGroupedCfgs];       // per grouped tile: workgroups of the launch
+  int heur;                          // the tile the work estimate picks
+  int variant;                       // gather variant shared by every problem of the launch
+  uint64_t sig;                      // the step's problems (shapes and variant), for the tile cache
 };
 
 struct BatchPlan {
@@ -115,8 +118,10 @@ bool is_contiguous(const tn_tensor& t) {
   return true;
 }
 
-// Tile size for one site step, shared by all of its problems (one launch per
-// step and product).  A step is usually too small to fill the chip with
+// Work estimate of the tile for one site step, shared by all of its problems
+// (one launch per step and product); used when tuning is off or the stream
+// is being captured.  With tuning on, the first launch of each step
+// signature and precision times the four grouped tiles instead.  A step is usually too small to fill the chip with
 // 128 x 128 tiles, so its time is the latency of one tile rather than the
 // total work: the estimate is, in units of one wave's 32 x 32 block times one
 // k, the larger of the longest wave's work and the total padded work spread
@@ -231,7 +236,6 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
     max_steps = std::max(max_steps, std::max(r.c, r.n - r.c));
   }
   P.chain_bytes = o;
-  const int forced = forced_grouped_cfg();
   for (int j = 0; j < max_steps; ++j) {
     for (int g = 0; g < 2; ++g) {
       std::vector<std::pair<int64_t, Gemm2D>> v;
@@ -328,18 +332,36 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
       Launch L;
       L.prob_off = P.probs.size();
       L.n_probs = (int32_t)v.size();
-      L.tile_off = P.tstart.size();
-      L.cfg = forced >= 0 ? forced : step_cfg(qs);
+      L.heur = step_cfg(qs);
       L.variant = var;
-      const int tm = grouped_tile_m(L.cfg), tn_ = grouped_tile_n(L.cfg);
-      int64_t t = 0;
+      // FNV-1a over the problem shapes in launch order and the variant
+      uint64_t h = 1469598103934665603ull;
+      auto mix = [&h](uint64_t x) {
+        for (int b = 0; b < 8; ++b) {
+          h ^= (x >> (8 * b)) & 0xffu;
+          h *= 1099511628211ull;
+        }
+      };
+      mix((uint64_t)var);
       for (const Gemm2D& q : qs) {
-        P.tstart.push_back((int32_t)t);
-        t += (int64_t)((q.M + tm - 1) / tm) * ((q.N + tn_ - 1) / tn_);
+        mix((uint64_t)q.M);
+        mix((uint64_t)q.N);
+        mix((uint64_t)q.K);
         P.probs.push_back(q);
       }
-      if (t >= (1ll << 31)) return fail(TN_ERR_UNSUPPORTED, "too many tiles in one step");
-      L.tiles = (int32_t)t;
+      L.sig = h;
+      // a tile-start table for every grouped tile, so the tile can be chosen per launch
+      for (int g2 = 0; g2 < kGroupedCfgs; ++g2) {
+        const int tm = grouped_tile_m(g2), tn_ = grouped_tile_n(g2);
+        L.tile_off[g2] = P.tstart.size();
+        int64_t t = 0;
+        for (const Gemm2D& q : qs) {
+          P.tstart.push_back((int32_t)t);
+          t += (int64_t)((q.M + tm - 1) / tm) * ((q.N + tn_ - 1) / tn_);
+        }
+        if (t >= (1ll << 31)) return fail(TN_ERR_UNSUPPORTED, "too many tiles in one step");
+        L.tiles[g2] = (int32_t)t;
+      }
       P.launches.push_back(L);
     }
   }
@@ -406,9 +428,49 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   int32_t* d_tiles = reinterpret_cast<int32_t*>(ws + Q.tile_tab);
   hipLaunchKernelGGL(batched_init_kernel, dim3(n_chains), dim3(64), 0, st, d_chains, n_chains);
   TN_TRY(hip_check(hipGetLastError(), "batched init"));
-  for (const Launch& L : Q.launches)
-    TN_TRY(launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off, L.n_probs, L.tiles, prec, L.cfg, L.variant,
-                               st));
+  const int forced = forced_grouped_cfg();
+  const int level = forced >= 0 ? 0 : tune_timing_level(st);
+  auto run = [&](const Launch& L, int cfg) {
+    return launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off[cfg], L.n_probs, L.tiles[cfg], prec, cfg,
+                               L.variant, st);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  for (const Launch& L : Q.launches) {
+    int cfg = forced >= 0 ? forced : grouped_tune_get(L.sig, prec);
+    if (cfg < 0) {
+      bool timed = false;
+      cfg = L.heur;
+      if (level > 0) {
+        // time every grouped tile on this step, with the step's real
+        // inputs (a launch only writes its own outputs, so repeating it
+        // recomputes the same values), and keep the fastest
+        if (!e0) {
+          TN_TRY(hip_check(hipEventCreate(&e0), "tuning event"));
+          TN_TRY(hip_check(hipEventCreate(&e1), "tuning event"));
+        }
+        float best = 1e30f;
+        const int reps = level >= 2 ? 10 : 3;
+        for (int c = 0; c < kGroupedCfgs; ++c) {
+          TN_TRY(run(L, c));
+          TN_TRY(hip_check(hipEventRecord(e0, st), "tuning event"));
+          for (int r = 0; r < reps; ++r) TN_TRY(run(L, c));
+          TN_TRY(hip_check(hipEventRecord(e1, st), "tuning event"));
+          TN_TRY(hip_check(hipEventSynchronize(e1), "tuning event"));
+          float ms = 0.f;
+          TN_TRY(hip_check(hipEventElapsedTime(&ms, e0, e1), "tuning event"));
+          if (ms < best) {
+            best = ms;
+            cfg = c;
+          }
+        }
+        timed = true;
+      }
+      grouped_tune_put(L.sig, prec, cfg, timed);
+    }
+    TN_TRY(run(L, cfg));
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
   hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(kFinishThreads), 0, st, d_chains, n_chains, out2);
   return hip_check(hipGetLastError(), "batched finish");
 }

@@ -151,6 +151,8 @@ using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
 static std::mutex g_tune_mu;
 static int g_tune_level = 0;
 static std::map<TuneKey, int> g_tune_cache;
+// grouped launches of the uneven batch: (step signature, precision) -> grouped tile
+static std::map<std::pair<uint64_t, int>, int> g_grouped_cache;
 static std::string g_tune_path;   // persisted cache file ("" = memory only)
 static thread_local int g_last_choice = -1;
 static thread_local bool g_no_timing = false;
@@ -160,13 +162,22 @@ NoTimingScope::~NoTimingScope() { g_no_timing = prev; }
 static std::once_flag g_env_once;
 static bool g_log = false;
 
-// "M N K batch amode bmode cmode prec groups -> cfg" per line; caller holds g_tune_mu
+// "M N K batch amode bmode cmode prec groups -> cfg" per line, and
+// "G signature prec -> cfg" (signature in hex) for the grouped launches;
+// caller holds g_tune_mu
 static void load_cache_file_locked() {
   if (g_tune_path.empty()) return;
   FILE* f = std::fopen(g_tune_path.c_str(), "r");
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == 'G') {
+      unsigned long long sig = 0;
+      int pr = 0, c = -1;
+      if (std::sscanf(line, "G %llx %d -> %d", &sig, &pr, &c) == 3 && c >= 0 && c < 4)
+        g_grouped_cache[std::make_pair((uint64_t)sig, pr)] = c;
+      continue;
+    }
     int v[10];
     if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d -> %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
                     &v[7], &v[8], &v[9]) != 10)
@@ -183,6 +194,14 @@ static void append_cache_file_locked(const TuneKey& k, int cfg) {
   if (!f) return;
   std::fprintf(f, "%d %d %d %d %d %d %d %d %d -> %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
                std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), cfg);
+  std::fclose(f);
+}
+
+static void append_grouped_line_locked(uint64_t sig, int prec, int cfg) {
+  if (g_tune_path.empty()) return;
+  FILE* f = std::fopen(g_tune_path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "G %llx %d -> %d\n", (unsigned long long)sig, prec, cfg);
   std::fclose(f);
 }
 
@@ -205,6 +224,32 @@ static void read_env() {
 bool log_enabled() {
   std::call_once(g_env_once, read_env);
   return g_log;
+}
+
+int tune_timing_level(hipStream_t st) {
+  log_enabled();
+  int level;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    level = g_tune_level;
+  }
+  if (level == 0 || g_no_timing) return 0;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 0;
+  return level;
+}
+
+int grouped_tune_get(uint64_t sig, int prec) {
+  log_enabled();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_grouped_cache.find(std::make_pair(sig, prec));
+  return it == g_grouped_cache.end() ? -1 : it->second;
+}
+
+void grouped_tune_put(uint64_t sig, int prec, int cfg, bool timed) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_grouped_cache[std::make_pair(sig, prec)] = cfg;
+  if (timed) append_grouped_line_locked(sig, prec, cfg);
 }
 
 int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st) {
@@ -358,6 +403,7 @@ int32_t tn_tune(const char* cache_path, int32_t level) {
   }
   tn::g_tune_level = level;
   tn::g_tune_cache.clear();
+  tn::g_grouped_cache.clear();
   tn::g_tune_path = cache_path ? cache_path : "";
   tn::load_cache_file_locked();
   return TN_OK;
@@ -369,6 +415,7 @@ int32_t tn_tune_set_level(int32_t level) {
   std::lock_guard<std::mutex> lk(tn::g_tune_mu);
   tn::g_tune_level = level;
   tn::g_tune_cache.clear();
+  tn::g_grouped_cache.clear();
   tn::load_cache_file_locked();
   return TN_OK;
 }

@@ -80,6 +80,13 @@ int grouped_tile_m(int cfg);
 int32_t side_stream(hipStream_t& out);
 // grouped tile configuration pinned by tn_tune_force_grouped_config, or -1
 int forced_grouped_cfg();
+// the tuning level when timing is allowed on st now (not disabled on this
+// thread, stream not capturing), else 0
+int tune_timing_level(hipStream_t st);
+// tuned grouped tile of a step (signature, precision), or -1; record a choice
+// (timed choices are appended to the tile cache file)
+int grouped_tune_get(uint64_t sig, int prec);
+void grouped_tune_put(uint64_t sig, int prec, int cfg, bool timed);
 int grouped_tile_n(int cfg);
 
 // ---- complex contraction on the real path (complex.hip) -----------------------

@@ -176,6 +176,47 @@ def test_inner_batched_every_grouped_tile(tile, prec):
         assert value_rel(got[i, 0], got[i, 1], mr, sr) <= 4 * TOL[prec], (tile, i)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_inner_batched_tuned_steps(prec, tmp_path):
+    """With tuning on, the first launch times the four grouped tiles on every
+    step (re-running a step's launch on its real inputs) and records one
+    choice per step signature and precision in the cache file; the results
+    match the oracle.  Later launches are served from the cache: the one
+    after a reload of the file times and appends nothing and repeats the
+    previous cached launch exactly."""
+    rng = np.random.default_rng(59)
+    chains, refs = [], []
+    for i, chi in enumerate([5, 24, 64, 130]):
+        n = int(rng.integers(6, 14))
+        psi, phi = inputs.uneven_chain(i, n, chi, seed=431)
+        psi, phi = r32(psi), r32(phi)
+        refs.append(oracle.mps_inner(psi, phi))
+        chains.append((g32(psi), g32(phi)))
+    path = tmp_path / "tiles.txt"
+    try:
+        tn.tune(path, 1)
+        out = tn.mps_inner_batched(chains, prec=prec)
+        torch.cuda.synchronize()
+        lines = [x for x in path.read_text().splitlines() if x.startswith("G ")]
+        assert lines, "no grouped choices recorded"
+        assert all(int(x.rsplit("->", 1)[1]) in (0, 1, 2, 3) for x in lines)
+        assert all(int(x.split()[2]) == {"fp32": 0, "split_bf16": 2}[prec] for x in lines)
+        again = tn.mps_inner_batched(chains, prec=prec)
+        torch.cuda.synchronize()
+        n_lines = len(lines)
+        tn.tune(path, 1)   # reload: every step is cached, nothing is timed or appended
+        third = tn.mps_inner_batched(chains, prec=prec)
+        torch.cuda.synchronize()
+        assert len([x for x in path.read_text().splitlines() if x.startswith("G ")]) == n_lines
+        np.testing.assert_array_equal(again.cpu().numpy(), third.cpu().numpy())
+    finally:
+        tn.tune(None, 0)
+    for res in (out, again):
+        got = res.cpu().numpy()
+        for i, (mr, sr) in enumerate(refs):
+            assert value_rel(got[i, 0], got[i, 1], mr, sr) <= 4 * TOL[prec], i
+
+
 # ---------------------------------------------------------------------------
 # environment sweeps
 
