@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "next", "batched", "canonicalize", "profile"],
+    ap.add_argument("--mode", choices=["sweep", "tensordot", "rows", "next", "batched", "canonicalize", "profile",
+                                       "mfma_rate"],
                     default="sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--chains", type=int, default=512, help="--mode batched: first N chains of the uneven batch")
@@ -149,6 +150,25 @@ def time_loop(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms
 
 
+RATE_FLOPS = 256 * 8 * 5 * 6 * 32768 * 64   # issued flops of one rate measurement = T1's split-BF16 products
+
+
+def product_rate(torch, tn, detail=False):
+    """Issued-MFMA fraction of the split-BF16 product chains alone
+    (tn_measure_split_mfma_rate at T1's issued flops), random then zero
+    operand bits, after half a second of the same work to settle the clock."""
+    out = torch.empty(131072, device="cuda:0")
+    for _ in range(6000):
+        tn.measure_split_mfma_rate(out, 64, False)
+    torch.cuda.synchronize()
+    res = {}
+    for zero in (False, True):
+        ms = time_loop(torch, lambda: tn.measure_split_mfma_rate(out, 64, zero), 200, 20)
+        frac = round(RATE_FLOPS / (ms * 1e-3) / PEAK["bf16"] / 1e12, 4)
+        res["zero" if zero else "random"] = {"us": round(1e3 * ms, 2), "issued_frac": frac} if detail else frac
+    return res
+
+
 HEAD_REPS = 20  # contractions per recorded graph in the headline loop
 
 
@@ -190,17 +210,22 @@ def headline(torch, tn, steps, warmup, graph=True, precs=("split_bf16", "fp32"))
     return flops, res, outs
 
 
-def traffic_for(kernel_key):
-    """HBM bytes per launch from the committed PMC summary, if it was taken on this kernel source."""
+def traffic_for(tile_config):
+    """HBM bytes per launch of the T1 split-BF16 GEMM from the committed PMC
+    summary, if it was taken on the tile the tuner chose here and on the
+    current source of that kernel."""
     p = os.path.join(ROOT, "profiles", "gemm_T1_split_bf16_traffic.json")
     if not os.path.exists(p):
         return None
     try:
         t = json.load(open(p))
-        src = open(os.path.join(ROOT, "paper_1905_01330_amd", "csrc", "gemm_kernel.h"), "rb").read()
-        if t.get("gemm_kernel_sha1") != hashlib.sha1(src).hexdigest():
+        if t.get("tile_config") != tile_config:
             return None
-        return t.get(kernel_key)
+        for name, sha in t.get("sources", {}).items():
+            src = open(os.path.join(ROOT, "paper_1905_01330_amd", "csrc", name), "rb").read()
+            if hashlib.sha1(src).hexdigest() != sha:
+                return None
+        return t.get("bytes_per_launch")
     except Exception:
         return None
 
@@ -721,6 +746,9 @@ def main():
         print(json.dumps({"mode": "canonicalize", "n_sites": N_SITES, "chi": CHI,
                           "ms_per_call": round(1e3 * sum(times) / max(len(times), 1), 3)}))
         return
+    if a.mode == "mfma_rate":
+        print(json.dumps({"mode": "mfma_rate", "issued_flops": RATE_FLOPS, **product_rate(torch, tn, detail=True)}))
+        return
     if a.mode == "tensordot":
         tn.tune_set_level(1)
         flops, res, _ = headline(torch, tn, a.steps, a.warmup, graph=False)
@@ -747,7 +775,8 @@ def main():
                                        precs=("split_bf16", "fp32", "bf16", "split_bf16_3p"))
     x6 = head["split_bf16"]
     achieved = x6["tflops"]
-    traffic = traffic_for("gemm_split_bf16_chi1024")
+    traffic = traffic_for(x6["tile_config"])
+    rate = product_rate(torch, tn)
 
     value = flops / (ms["split_bf16"] * 1e-3) / 1e12
     line = {
@@ -779,6 +808,9 @@ def main():
             "issued_mfma_frac": round(6 * achieved / PEAK["bf16"], 4),
             "launch_ms": round(x6["ms"], 5),
             "tile_config": x6["tile_config"],
+            # the same six-product chains with register operands (no loads,
+            # no LDS), random and zero operand bits: what the chip sustains
+            "product_rate_issued_frac": rate,
         },
         "fp32_path": {
             "value": round(flops / (ms["fp32"] * 1e-3) / 1e12, 3),

@@ -446,6 +446,22 @@ int32_t tn_tune_last_choice(void);
  * Meant for measurement. */
 int32_t tn_tune_force_config(int32_t cfg);
 int32_t tn_tune_num_configs(void);
+/* Measurement: the matrix-core rate of the split-BF16 term products alone.
+ * One launch runs 256 x 8 waves, each wave five 32 x 32 blocks over n_steps
+ * k-steps of 16 with the six BF16 term products per block and step chained
+ * from zero and added to the FP32 accumulator every two steps, as the
+ * contraction kernels do, with register operands: no loads, no LDS.  For
+ * reading the contraction GEMM's matrix-core fraction against what the
+ * chip sustains for the same products.  At
+ * n_steps = 64 it issues the same 1.288e11 flops as the split-BF16 product
+ * of the bulk-site contraction M = 5120, K = 1024, N = 2048.  zero_operands
+ * = 0 fills the operands with hashed bits (random mantissas), 1 with zeros:
+ * the chip's clock under this load depends on the bits the matrix cores
+ * toggle.  out: DEVICE, 131072 floats (one per lane; overwritten).
+ * TN_ERR_INVALID_ARGUMENT for a NULL out or an odd or non-positive
+ * n_steps. */
+int32_t tn_measure_split_mfma_rate(int32_t n_steps, int32_t zero_operands, float* out, void* stream);
+
 /* Pin the tile of every site step of the uneven batched inner product:
  * 0: 128 x 128, 1: 64 x 64, 2: 32 x 32, 3: 64 x 64 in two k-slices; -1
  * restores the per-step choice (tuned or estimated).  The upload writes the

@@ -33,6 +33,7 @@ from .api import (  # noqa: F401
     tune_force_grouped_config,
     tune_last_choice,
     tune_num_configs,
+    measure_split_mfma_rate,
     tune_set_level,
 )
 

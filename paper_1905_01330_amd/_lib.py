@@ -90,6 +90,7 @@ _PROTOS = {
     "tn_tune_force_config": (I32, [I32]),
     "tn_tune_force_grouped_config": (I32, [I32]),
     "tn_tune_num_configs": (I32, []),
+    "tn_measure_split_mfma_rate": (I32, [I32, I32, P, P]),
 }
 
 

@@ -463,6 +463,15 @@ def tune_num_configs() -> int:
     return int(L.lib().tn_tune_num_configs())
 
 
+def measure_split_mfma_rate(out, n_steps: int = 64, zero_operands: bool = False):
+    """Launch the split-BF16 term-product rate measurement on the current
+    stream (tn_measure_split_mfma_rate); out: CUDA float32 tensor of 131072
+    elements."""
+    if out.dtype != torch.float32 or not out.is_cuda or out.numel() < 131072:
+        raise ValueError("out must be a CUDA float32 tensor of at least 131072 elements")
+    L.check(L.lib().tn_measure_split_mfma_rate(int(n_steps), int(bool(zero_operands)), out.data_ptr(), L.stream_ptr()))
+
+
 # ---------------------------------------------------------------------------
 # MPS classifier (section IV.A)
 

@@ -186,6 +186,18 @@ def test_tuner_controls():
     assert lib.tn_tune_set_level(0) == 0
 
 
+def test_mfma_rate_measurement_validation():
+    """The rate measurement rejects a NULL output and an odd or non-positive
+    step count before it launches anything."""
+    import ctypes as C
+    lib = L.lib()
+    buf = C.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    assert lib.tn_measure_split_mfma_rate(64, 0, None, None) == -1
+    assert lib.tn_measure_split_mfma_rate(63, 0, buf, None) == -1
+    assert lib.tn_measure_split_mfma_rate(0, 1, buf, None) == -1
+    assert lib.tn_measure_split_mfma_rate(-2, 0, buf, None) == -1
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
     import paper_1905_01330_amd as tn
