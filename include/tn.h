@@ -25,7 +25,11 @@
  *  - Real arithmetic unless a call says otherwise (the *_c64 calls take
  *    complex tensors and conjugation flags).
  *  - Calls on different streams may run concurrently; calls that write the
- *    same workspace or output on overlapping streams race.
+ *    same workspace or output on overlapping streams race.  Calls that fork
+ *    part of their work to a library side stream (the two-ended inner
+ *    product, the two-direction sweep, canonicalisation) take the side
+ *    stream assigned to their own stream: each device has four, given to
+ *    caller streams in turn.
  */
 #ifndef TN_H
 #define TN_H

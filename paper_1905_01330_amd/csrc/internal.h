@@ -74,10 +74,13 @@ int grouped_variant(const Gemm2D& p);
 int32_t launch_gemm_grouped(const Gemm2D* dev_probs, const int32_t* dev_tile_start, int32_t n_probs,
                             int32_t total_tiles, int32_t prec, int cfg, int variant, hipStream_t st);
 int grouped_tile_m(int cfg);
-// the library's second stream on the current device (created on first use,
-// default priority, never destroyed): work forked from and joined back into
-// the caller's stream by events
-int32_t side_stream(hipStream_t& out);
+// the library's side stream for the caller's stream s on the current device
+// (s in, side stream out): one of a pool of four per device (created on first
+// use, default priority, never destroyed), assigned to caller streams in
+// turn and kept, so calls on up to four different streams do not queue
+// behind each other's side work.  Work is forked from and joined back into
+// the caller's stream by events.
+int32_t side_stream(hipStream_t& s);
 // grouped tile configuration pinned by tn_tune_force_grouped_config, or -1
 int forced_grouped_cfg();
 // the tuning level when timing is allowed on st now (not disabled on this

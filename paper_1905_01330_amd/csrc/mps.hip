@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -506,15 +507,33 @@ static EnvLayout env_layout(int32_t n, const std::vector<int64_t>& dims, const s
 
 // A second stream per device (default priority) on which the right sweep
 // runs beside the left one; created on first use and kept for the process.
-int32_t side_stream(hipStream_t& out) {
+int32_t side_stream(hipStream_t& s) {
+  constexpr int kPool = 4;
+  struct DevPool {
+    hipStream_t streams[kPool] = {};
+    std::map<uintptr_t, int> slot_of;   // caller stream -> pool slot, assigned in turn
+    int next = 0;
+  };
   static std::mutex mu;
-  static std::vector<hipStream_t> streams;
+  static std::vector<DevPool> pools;
   int dev = 0;
   TN_TRY(hip_check(hipGetDevice(&dev), "get device"));
   std::lock_guard<std::mutex> lk(mu);
-  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
-  if (!streams[dev]) TN_TRY(hip_check(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking), "create stream"));
-  out = streams[dev];
+  if ((int)pools.size() <= dev) pools.resize(dev + 1);
+  DevPool& P = pools[dev];
+  const uintptr_t key = reinterpret_cast<uintptr_t>(s);
+  auto it = P.slot_of.find(key);
+  int slot;
+  if (it != P.slot_of.end()) {
+    slot = it->second;
+  } else {
+    slot = P.next;
+    P.next = (P.next + 1) % kPool;
+    P.slot_of[key] = slot;
+  }
+  if (!P.streams[slot])
+    TN_TRY(hip_check(hipStreamCreateWithFlags(&P.streams[slot], hipStreamNonBlocking), "create stream"));
+  s = P.streams[slot];
   return TN_OK;
 }
 

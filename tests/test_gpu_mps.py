@@ -258,6 +258,33 @@ def test_env_sweep_vs_oracle(model, prec):
         assert errl <= 1.2 * e32l and errr <= 1.2 * e32r, (errl, errr, e32l, e32r)
 
 
+def test_concurrent_calls_on_several_streams():
+    """Two-direction sweeps and two-ended inner products issued on three
+    caller streams at once (each forks to the side stream assigned to its
+    stream) give the same results, bit for bit, as the same calls made one
+    after another on the default stream."""
+    n, chi = 24, 64
+    psi = canonical(n, chi, 211)
+    mpo = inputs.xxz_mpo(n, 0.5)
+    gp, gm = g32(psi), g32(mpo)
+    ref_sweep = tn.mps_env_sweep(gp, gm, prec="split_bf16")
+    ref_inner = tn.mps_inner(gp, gp, prec="fp32")
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs = []
+    for rep in range(2):
+        for st in streams:
+            st.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st):
+                outs.append((tn.mps_env_sweep(gp, gm, prec="split_bf16"), tn.mps_inner(gp, gp, prec="fp32")))
+    torch.cuda.synchronize()
+    for (ls, rs, e), inner in outs:
+        for k in range(n + 1):
+            assert torch.equal(ls[k], ref_sweep[0][k]) and torch.equal(rs[k], ref_sweep[1][k]), k
+        assert torch.equal(e, ref_sweep[2])
+        assert torch.equal(inner, ref_inner)
+
+
 def test_env_sweep_cfg2_full():
     """N = 100, chi = 256, TFIM (J = g = 1), canonical random MPS: FP32 vs the oracle."""
     n, chi = 100, 256
