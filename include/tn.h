@@ -422,6 +422,11 @@ int32_t tn_dmrg_eigensolve(const tn_tensor* L, const tn_tensor* R, const tn_tens
  * the first launch of each (step signature, precision) times its four
  * grouped tiles, re-running the step on its real inputs, and keeps the
  * fastest.
+ * The GEMMs of a two-direction environment sweep and of a two-ended inner
+ * product share the chip with the other direction's stream: they are
+ * chosen apart from the same GEMMs issued alone (their cache lines carry
+ * 1000 added to the groups field), estimated for half the compute units
+ * and timed as two copies issued together on two streams.
  * Tile choices are cached per process; the cache is mutex-guarded, so
  * concurrent calls from several threads are safe.  Timing is skipped while
  * the stream is being captured into a graph (the heuristic is used then).

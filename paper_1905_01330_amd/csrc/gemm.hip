@@ -9,6 +9,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "gemm_inst.h"
 
@@ -123,10 +124,19 @@ static bool cfg_allowed(const GemmDesc& d, int prec, int c) {
   return g.wm * g.wn * g.wk < 8 || g.bm * g.bn <= 64 * 64 || gemm_variant(d) != 0;
 }
 
+// set while the calling thread issues GEMMs that share the chip with a
+// concurrent stream (the two halves of a two-directional sweep)
+static thread_local bool g_shared = false;
+
+SharedChipScope::SharedChipScope(bool on) : prev(g_shared) { g_shared = prev || on; }
+SharedChipScope::~SharedChipScope() { g_shared = prev; }
+
 static int heuristic_cfg(const GemmDesc& d, int prec) {
   const int forced = g_forced_cfg.load();
   if (forced >= 0) return forced;
-  constexpr int kSlots = 256;  // one workgroup per compute unit for the large tiles
+  // one workgroup per compute unit for the large tiles; a GEMM that shares
+  // the chip with a concurrent stream counts on half of them
+  const int kSlots = g_shared ? 128 : 256;
   double best = 1e300;
   int best_c = 7;   // 32 x 32 tiles fit every problem
   for (int c = 0; c < kNumCfgs; ++c) {
@@ -282,11 +292,39 @@ int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st) {
   return hip_check(hipGetLastError(), "gemm launch");
 }
 
+// the stream on which the tuner runs the second copy of a GEMM that shares
+// the chip (one per device, default priority, created on first use)
+static int32_t twin_stream(hipStream_t& hs) {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  int dev = 0;
+  TN_TRY(hip_check(hipGetDevice(&dev), "get device"));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev]) TN_TRY(hip_check(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking), "create stream"));
+  hs = streams[dev];
+  return TN_OK;
+}
+
+// Times every allowed tile on the real operands and returns the fastest.  A
+// GEMM that shares the chip is timed as two copies issued together on st
+// and on a twin stream, the way the two directions of a sweep overlap: a
+// tile that fills the chip alone then queues behind its twin, while one
+// that needs half the compute units runs beside it.  Both copies write the
+// same values to C (deterministic kernels; |C| maxima are idempotent), and
+// the real launch that follows on st overwrites them after the twin is done.
 static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
-  hipEvent_t e0, e1;
+  hipStream_t hs = nullptr;
+  if (g_shared && twin_stream(hs) != TN_OK) hs = nullptr;
+  hipEvent_t e0, e1, ej;
   if (hipEventCreate(&e0) != hipSuccess) return heuristic_cfg(d, prec);
   if (hipEventCreate(&e1) != hipSuccess) {
     hipEventDestroy(e0);
+    return heuristic_cfg(d, prec);
+  }
+  if (hipEventCreateWithFlags(&ej, hipEventDisableTiming) != hipSuccess) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
     return heuristic_cfg(d, prec);
   }
   int best = heuristic_cfg(d, prec);
@@ -297,8 +335,16 @@ static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
     if (!cfg_allowed(d, prec, c)) continue;
     if (launch_gemm_cfg(d, prec, c, st) != TN_OK) continue;  // warm-up
     hipEventRecord(e0, st);
+    if (hs) hipStreamWaitEvent(hs, e0, 0);
     const int reps = level >= 2 ? 10 : 3;
-    for (int r = 0; r < reps; ++r) launch_gemm_cfg(d, prec, c, st);
+    for (int r = 0; r < reps; ++r) {
+      launch_gemm_cfg(d, prec, c, st);
+      if (hs) launch_gemm_cfg(d, prec, c, hs);
+    }
+    if (hs) {
+      hipEventRecord(ej, hs);
+      hipStreamWaitEvent(st, ej, 0);
+    }
     hipEventRecord(e1, st);
     hipEventSynchronize(e1);
     float ms = 0.f;
@@ -310,6 +356,7 @@ static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  hipEventDestroy(ej);
   return best;
 }
 
@@ -324,8 +371,9 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
   }
   int cfg;
   int level;
+  // GEMMs sharing the chip are chosen apart: 1000 added to the groups field
   const TuneKey key = std::make_tuple(d.M, d.N, d.K, d.batch, d.a_mode, d.b_mode, d.c_mode, (int)prec,
-                                      (int)(d.gm.n * 100 + d.gn.n * 10 + d.gk.n));
+                                      (int)(d.gm.n * 100 + d.gn.n * 10 + d.gk.n + (g_shared ? 1000 : 0)));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     level = g_tune_level;
@@ -357,10 +405,10 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
   if (log) {
     const Cfg& g = kCfgs[cfg];
     std::fprintf(stderr,
-                 "[tn] gemm M=%d N=%d K=%d batch=%d groups(m,n,k)=(%d,%d,%d) modes(a,b,c)=(%d,%d,%d) prec=%d -> "
+                 "[tn] gemm M=%d N=%d K=%d batch=%d groups(m,n,k)=(%d,%d,%d) modes(a,b,c)=(%d,%d,%d) prec=%d%s -> "
                  "tile %d (%dx%dx%d, %dx%dx%d waves) %s\n",
-                 d.M, d.N, d.K, d.batch, d.gm.n, d.gn.n, d.gk.n, d.a_mode, d.b_mode, d.c_mode, (int)prec, cfg, g.bm,
-                 g.bn, g.bk, g.wm, g.wn, g.wk, how);
+                 d.M, d.N, d.K, d.batch, d.gm.n, d.gn.n, d.gk.n, d.a_mode, d.b_mode, d.c_mode, (int)prec,
+                 g_shared ? " shared" : "", cfg, g.bm, g.bn, g.bk, g.wm, g.wn, g.wk, how);
   }
   g_last_choice = cfg;
   return launch_gemm_cfg(d, prec, cfg, st);

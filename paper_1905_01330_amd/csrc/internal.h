@@ -52,6 +52,16 @@ struct NoTimingScope {
   ~NoTimingScope();
   bool prev;
 };
+// While one of these lives on a thread, launch_gemm on that thread serves
+// GEMMs that share the chip with a concurrent stream (the two halves of a
+// two-directional sweep or inner product): tiles are estimated for half the
+// compute units, timed as two copies running at once, and cached apart
+// from the same GEMM issued alone.
+struct SharedChipScope {
+  explicit SharedChipScope(bool on = true);
+  ~SharedChipScope();
+  bool prev;
+};
 // K <= 32 with N or M <= 16 (and no batch, scale or max-abs): the HBM-bound path
 bool gemm_small_fits(const GemmDesc& d);
 int32_t launch_gemm_small(const GemmDesc& d, int32_t prec, hipStream_t st);

@@ -637,11 +637,14 @@ int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi
   hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(c + 1)), dim3(256), 0, st, e[0], slots, c + 1);
   hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(nr + 1)), dim3(256), 0, rs, er[0], rslots, nr + 1);
   int32_t rc = hip_check(hipGetLastError(), "mps init");
-  for (int i = 0; i < std::max(c, nr) && rc == TN_OK; ++i) {
-    if (i < c) rc = inner_site(psi[i], phi[i], e[i & 1], e[(i + 1) & 1], t, slots, i, prec, st);
-    if (rc == TN_OK && i < nr) {
-      const int k = n_sites - 1 - i;
-      rc = inner_site_right(psi[k], phi[k], er[i & 1], er[(i + 1) & 1], tr, rslots + i, rslots + i + 1, prec, rs);
+  {
+    SharedChipScope shared;
+    for (int i = 0; i < std::max(c, nr) && rc == TN_OK; ++i) {
+      if (i < c) rc = inner_site(psi[i], phi[i], e[i & 1], e[(i + 1) & 1], t, slots, i, prec, st);
+      if (rc == TN_OK && i < nr) {
+        const int k = n_sites - 1 - i;
+        rc = inner_site_right(psi[k], phi[k], er[i & 1], er[(i + 1) & 1], tr, rslots + i, rslots + i + 1, prec, rs);
+      }
     }
   }
   hipEventRecord(join, rs);
@@ -796,9 +799,12 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
     hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, rs, static_cast<float*>(rcur.data));
   }
   int32_t rc = TN_OK;
-  for (int i = 0; i < n_sites && rc == TN_OK; ++i) {
-    if (which & 1) rc = left_site(i, lcur, st);
-    if (rc == TN_OK && (which & 2)) rc = right_site(n_sites - 1 - i, rcur, rs);
+  {
+    SharedChipScope shared(which == 3);
+    for (int i = 0; i < n_sites && rc == TN_OK; ++i) {
+      if (which & 1) rc = left_site(i, lcur, st);
+      if (rc == TN_OK && (which & 2)) rc = right_site(n_sites - 1 - i, rcur, rs);
+    }
   }
   if (which == 3) {
     hipEventRecord(join, rs);

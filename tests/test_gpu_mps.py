@@ -285,6 +285,50 @@ def test_concurrent_calls_on_several_streams():
         assert torch.equal(inner, ref_inner)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_env_sweep_tuned_shared_chip(prec, tmp_path):
+    """With tuning on, the GEMMs of a two-direction sweep, which share the
+    chip with the other direction, are timed as pairs and recorded under a
+    key of their own (1000 added to the groups field); the same GEMMs in a
+    one-direction sweep are recorded apart.  Results match the oracle, and
+    after a reload of the file every choice is served from it (nothing is
+    appended) with bit-identical results."""
+    n, chi = 16, 96
+    psi = canonical(n, chi, 223)
+    mpo = inputs.xxz_mpo(n, 0.5)
+    ls_ref, rs_ref, _, _ = oracle.env_sweep(psi, mpo)
+    gp, gm = g32(psi), g32(mpo)
+    path = tmp_path / "tiles.txt"
+
+    def keys():
+        return [x.split("->")[0].split() for x in path.read_text().splitlines() if x and not x.startswith("G ")]
+
+    try:
+        tn.tune(path, 1)
+        ls, rs, e = tn.mps_env_sweep(gp, gm, prec=prec)
+        torch.cuda.synchronize()
+        both = keys()
+        assert both and all(int(k[8]) >= 1000 for k in both), both
+        ls1, _, _ = tn.mps_env_sweep(gp, gm, right=False, prec=prec)
+        torch.cuda.synchronize()
+        one = keys()[len(both):]
+        assert one and all(int(k[8]) < 1000 for k in one), one
+        n_lines = len(keys())
+        tn.tune(path, 1)   # reload
+        ls2, rs2, e2 = tn.mps_env_sweep(gp, gm, prec=prec)
+        torch.cuda.synchronize()
+        assert len(keys()) == n_lines
+    finally:
+        tn.tune(None, 0)
+    errl, errr = env_errors(ls, rs, ls_ref, rs_ref)
+    assert errl <= TOL[prec] and errr <= TOL[prec], (errl, errr)
+    errl1, _ = env_errors(ls1, rs, ls_ref, rs_ref)
+    assert errl1 <= TOL[prec], errl1
+    for k in range(n + 1):
+        assert torch.equal(ls[k], ls2[k]) and torch.equal(rs[k], rs2[k]), k
+    assert torch.equal(e, e2)
+
+
 def test_env_sweep_cfg2_full():
     """N = 100, chi = 256, TFIM (J = g = 1), canonical random MPS: FP32 vs the oracle."""
     n, chi = 100, 256
