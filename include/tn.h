@@ -268,7 +268,10 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
  * or NULL to skip that direction's stores (the sweep still runs when energy
  * is requested).  energy2 (DEVICE, 2 doubles, nullable): [L_N, R_0].
  * which: bit 0 = left sweep, bit 1 = right sweep.
- * Each site is three steps: ket-site GEMM, MPO step, bra-site GEMM.
+ * Each site is three steps: ket-site GEMM, MPO step, bra-site GEMM.  A
+ * GEMM that fills few compute units (small bond dimensions) may run as
+ * k-slices into the workspace, added in slice order by a second kernel
+ * (the tuner's choice, deterministic for a given choice).
  * With both bits set the right sweep runs on a second stream that the
  * library owns (one per device, default priority), forked from `stream`
  * by an event before its first launch and joined back into `stream`
@@ -433,7 +436,9 @@ int32_t tn_dmrg_eigensolve(const tn_tensor* L, const tn_tensor* R, const tn_tens
  *
  * tn_tune(cache_path, level): sets the level and, when cache_path is not
  * NULL, persists the choices in that text file: entries already in it are
- * loaded now (lines "M N K batch amode bmode cmode prec groups -> cfg" and
+ * loaded now (lines "M N K batch amode bmode cmode prec groups -> choice",
+ * choice = tile + 100 log2(k-slices) (k-slices only inside the environment
+ * sweep, which holds their scratch), and
  * "G step-signature prec -> grouped tile", malformed lines are skipped) and
  * every timed choice made later is appended.
  * NULL keeps the choices in memory only.  Changing the level clears the

@@ -131,6 +131,80 @@ static thread_local bool g_shared = false;
 SharedChipScope::SharedChipScope(bool on) : prev(g_shared) { g_shared = prev || on; }
 SharedChipScope::~SharedChipScope() { g_shared = prev; }
 
+// k-slice scratch of the calling thread (SplitKScope), in floats
+static thread_local float* g_splitk = nullptr;
+static thread_local size_t g_splitk_floats = 0;
+
+SplitKScope::SplitKScope(float* scratch, size_t floats) : prev_p(g_splitk), prev_n(g_splitk_floats) {
+  g_splitk = scratch;
+  g_splitk_floats = floats;
+}
+SplitKScope::~SplitKScope() {
+  g_splitk = prev_p;
+  g_splitk_floats = prev_n;
+}
+
+// A choice is a tile configuration and a k-slice count 2^lg, kept as
+// cfg + 100 lg (lg = 0: the GEMM runs whole).
+static int choice_cfg(int v) { return v % 100; }
+static int choice_lg(int v) { return v / 100; }
+constexpr int kMaxSliceLg = 2;
+
+// Whether the GEMM can run as 2^lg k-slices into the scratch: one merged
+// contracted axis (a slice is a pointer offset), no batch, no per-batch
+// scale or |C| maximum, slices of whole 16-k steps and at least 64 long,
+// and room for the 2^lg dense M x N partial results.
+static bool slices_ok(const GemmDesc& d, int lg) {
+  if (lg == 0) return true;
+  const int S = 1 << lg;
+  return g_splitk && d.batch == 1 && d.gk.n == 1 && !d.a_scale_bits && !d.c_absmax && d.K % (16 * S) == 0 &&
+         d.K / S >= 64 && (size_t)S * (size_t)d.M * (size_t)d.N <= g_splitk_floats;
+}
+
+// The slices as a batch of S GEMMs: slice z contracts k in [z K/S, (z+1) K/S)
+// (A and B advanced by K/S steps of their k stride) into the dense M x N
+// partial z of the scratch.
+static GemmDesc slice_desc(const GemmDesc& d, int S) {
+  GemmDesc x = d;
+  const int Ks = d.K / S;
+  x.K = Ks;
+  x.gk.dim[0] = (uint32_t)Ks;
+  set_fast_div(x.gk);
+  x.batch = S;
+  x.a_bs = (int64_t)Ks * d.gk.s[0][0];
+  x.b_bs = (int64_t)Ks * d.gk.s[1][0];
+  x.c = g_splitk;
+  x.c_bs = (int64_t)d.M * d.N;
+  int64_t st = d.N;
+  for (int i = x.gm.n - 1; i >= 0; --i) {
+    x.gm.s[1][i] = st;
+    st *= x.gm.dim[i];
+  }
+  st = 1;
+  for (int i = x.gn.n - 1; i >= 0; --i) {
+    x.gn.s[1][i] = st;
+    st *= x.gn.dim[i];
+  }
+  choose_modes(x);
+  return x;
+}
+
+// C[m, n] = the partials' sum over the slices in slice order (deterministic),
+// stored through C's index groups
+__global__ void __launch_bounds__(256) slice_sum_kernel(const float* __restrict__ part, int S, int M, int N,
+                                                        float* __restrict__ c, const Group gm, const Group gn) {
+  const int64_t MN = (int64_t)M * N;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= MN) return;
+  const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
+  float s = part[i];
+  for (int z = 1; z < S; ++z) s += part[z * MN + i];
+  int64_t om[1], on[1];
+  group_offsets<1>(gm, (uint32_t)m, om, 1);
+  group_offsets<1>(gn, (uint32_t)n, on, 1);
+  c[om[0] + on[0]] = s;
+}
+
 static int heuristic_cfg(const GemmDesc& d, int prec) {
   const int forced = g_forced_cfg.load();
   if (forced >= 0) return forced;
@@ -192,7 +266,7 @@ static void load_cache_file_locked() {
     if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d -> %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
                     &v[7], &v[8], &v[9]) != 10)
       continue;
-    if (v[9] < 0 || v[9] >= kNumCfgs) continue;
+    if (v[9] < 0 || choice_cfg(v[9]) >= kNumCfgs || choice_lg(v[9]) > kMaxSliceLg) continue;
     g_tune_cache[std::make_tuple(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8])] = v[9];
   }
   std::fclose(f);
@@ -292,6 +366,36 @@ int32_t launch_gemm_cfg(GemmDesc& d, int32_t prec, int cfg, hipStream_t st) {
   return hip_check(hipGetLastError(), "gemm launch");
 }
 
+static int32_t launch_choice(GemmDesc& d, int32_t prec, int v, hipStream_t st) {
+  const int cfg = choice_cfg(v), lg = choice_lg(v);
+  if (lg == 0 || !slices_ok(d, lg)) return launch_gemm_cfg(d, prec, cfg, st);
+  const int S = 1 << lg;
+  GemmDesc x = slice_desc(d, S);
+  TN_TRY(launch_gemm_cfg(x, prec, cfg, st));
+  const int64_t MN = (int64_t)d.M * d.N;
+  hipLaunchKernelGGL(slice_sum_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, g_splitk, S, d.M, d.N,
+                     d.c, d.gm, d.gn);
+  return hip_check(hipGetLastError(), "k-slice sum");
+}
+
+// tiles of configuration c on the caller's problem
+static int64_t cfg_tiles(const GemmDesc& d, int c) {
+  const Cfg& g = kCfgs[c];
+  return (int64_t)((d.M + g.bm - 1) / g.bm) * ((d.N + g.bn - 1) / g.bn) * d.batch;
+}
+
+// the heuristic choice: the estimated tile, cut into k-slices when its tiles
+// fill at most half the compute units it can count on (a quarter for four
+// slices) and every slice keeps at least 128 of k
+static int heuristic_choice(const GemmDesc& d, int prec) {
+  const int c = heuristic_cfg(d, prec);
+  if (!g_splitk || g_forced_cfg.load() >= 0) return c;
+  const int64_t slots = g_shared ? 128 : 256, tiles = cfg_tiles(d, c);
+  for (int lg = kMaxSliceLg; lg >= 1; --lg)
+    if (slices_ok(d, lg) && tiles << lg <= slots && d.K >> lg >= 128) return c + 100 * lg;
+  return c;
+}
+
 // the stream on which the tuner runs the second copy of a GEMM that shares
 // the chip (one per device, default priority, created on first use)
 static int32_t twin_stream(hipStream_t& hs) {
@@ -327,19 +431,23 @@ static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
     hipEventDestroy(e1);
     return heuristic_cfg(d, prec);
   }
-  int best = heuristic_cfg(d, prec);
+  int best = heuristic_choice(d, prec);
   float best_ms = 1e30f;
-  for (int c = 0; c < kNumCfgs; ++c) {
+  for (int v = 0; v < kNumCfgs * (kMaxSliceLg + 1); ++v) {
+    const int c = v % kNumCfgs, lg = v / kNumCfgs;
     const Cfg& g = kCfgs[c];
     if ((int64_t)g.bm * g.bn > 4ll * d.M * d.N && c != 7) continue;  // mostly padding (32 x 32 always runs)
     if (!cfg_allowed(d, prec, c)) continue;
-    if (launch_gemm_cfg(d, prec, c, st) != TN_OK) continue;  // warm-up
+    // k-slices only where the whole GEMM leaves most compute units idle
+    if (lg > 0 && (!slices_ok(d, lg) || cfg_tiles(d, c) << lg > 512 || cfg_tiles(d, c) >= 256)) continue;
+    const int choice = c + 100 * lg;
+    if (launch_choice(d, prec, choice, st) != TN_OK) continue;  // warm-up
     hipEventRecord(e0, st);
     if (hs) hipStreamWaitEvent(hs, e0, 0);
     const int reps = level >= 2 ? 10 : 3;
     for (int r = 0; r < reps; ++r) {
-      launch_gemm_cfg(d, prec, c, st);
-      if (hs) launch_gemm_cfg(d, prec, c, hs);
+      launch_choice(d, prec, choice, st);
+      if (hs) launch_choice(d, prec, choice, hs);
     }
     if (hs) {
       hipEventRecord(ej, hs);
@@ -351,7 +459,7 @@ static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
     hipEventElapsedTime(&ms, e0, e1);
     if (ms < best_ms) {
       best_ms = ms;
-      best = c;
+      best = choice;
     }
   }
   hipEventDestroy(e0);
@@ -392,26 +500,27 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
         cfg = tune_cfg(d, prec, level, st);
         timed = true;
       } else {
-        cfg = heuristic_cfg(d, prec);
+        cfg = heuristic_choice(d, prec);
       }
     } else {
-      cfg = heuristic_cfg(d, prec);
+      cfg = heuristic_choice(d, prec);
     }
     how = timed ? "timed" : "heuristic";
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = cfg;
     if (timed) append_cache_file_locked(key, cfg);
   }
+  const int lg = slices_ok(d, choice_lg(cfg)) ? choice_lg(cfg) : 0;
   if (log) {
-    const Cfg& g = kCfgs[cfg];
+    const Cfg& g = kCfgs[choice_cfg(cfg)];
     std::fprintf(stderr,
                  "[tn] gemm M=%d N=%d K=%d batch=%d groups(m,n,k)=(%d,%d,%d) modes(a,b,c)=(%d,%d,%d) prec=%d%s -> "
-                 "tile %d (%dx%dx%d, %dx%dx%d waves) %s\n",
+                 "tile %d (%dx%dx%d, %dx%dx%d waves) x%d k-slices %s\n",
                  d.M, d.N, d.K, d.batch, d.gm.n, d.gn.n, d.gk.n, d.a_mode, d.b_mode, d.c_mode, (int)prec,
-                 g_shared ? " shared" : "", cfg, g.bm, g.bn, g.bk, g.wm, g.wn, g.wk, how);
+                 g_shared ? " shared" : "", choice_cfg(cfg), g.bm, g.bn, g.bk, g.wm, g.wn, g.wk, 1 << lg, how);
   }
-  g_last_choice = cfg;
-  return launch_gemm_cfg(d, prec, cfg, st);
+  g_last_choice = choice_cfg(cfg);
+  return launch_choice(d, prec, choice_cfg(cfg) + 100 * lg, st);
 }
 
 // the gather modes the grouped kernel derives for problem p (the same rules)

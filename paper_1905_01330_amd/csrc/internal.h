@@ -62,6 +62,19 @@ struct SharedChipScope {
   ~SharedChipScope();
   bool prev;
 };
+// While one of these lives on a thread, launch_gemm on that thread may cut
+// a GEMM that fills few compute units into k-slices: the slices run as one
+// batched launch into dense partial results in `scratch` (device, at least
+// `floats` floats; the caller's, not shared with concurrent work) and a
+// second kernel adds them in slice order into C.  The tuner times the slice
+// counts beside the tiles; the choice is cached with the tile (the cache
+// value is tile + 100 log2(slices)).
+struct SplitKScope {
+  SplitKScope(float* scratch, size_t floats);
+  ~SplitKScope();
+  float* prev_p;
+  size_t prev_n;
+};
 // K <= 32 with N or M <= 16 (and no batch, scale or max-abs): the HBM-bound path
 bool gemm_small_fits(const GemmDesc& d);
 int32_t launch_gemm_small(const GemmDesc& d, int32_t prec, hipStream_t st);

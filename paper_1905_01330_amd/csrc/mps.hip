@@ -481,8 +481,14 @@ static unsigned grid_for(int64_t n) {
 }
 
 struct EnvLayout {
-  size_t t1, t2, t1r, t2r, lbuf0, lbuf1, rbuf0, rbuf1, total;
+  size_t t1, t2, t1r, t2r, lbuf0, lbuf1, rbuf0, rbuf1, sk, skr, total;
+  size_t sk_floats;   // k-slice partials per direction
 };
+
+// k-slice scratch per direction: four partial results of the largest site
+// intermediate, at most 8 Mi floats (the GEMMs that k-slices help are the
+// small ones)
+constexpr int64_t kSliceScratchFloats = 1ll << 23;
 
 static EnvLayout env_layout(int32_t n, const std::vector<int64_t>& dims, const std::vector<int64_t>& w, int64_t d) {
   int64_t mt = 1, me = 1;
@@ -501,7 +507,10 @@ static EnvLayout env_layout(int32_t n, const std::vector<int64_t>& dims, const s
   L.lbuf1 = L.lbuf0 + align256(me * 4);
   L.rbuf0 = L.lbuf1 + align256(me * 4);
   L.rbuf1 = L.rbuf0 + align256(me * 4);
-  L.total = L.rbuf1 + align256(me * 4);
+  L.sk_floats = (size_t)std::min<int64_t>(4 * std::max(mt, me), kSliceScratchFloats);
+  L.sk = L.rbuf1 + align256(me * 4);
+  L.skr = L.sk + align256(L.sk_floats * 4);
+  L.total = L.skr + align256(L.sk_floats * 4);
   return L;
 }
 
@@ -705,9 +714,12 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
   float* t2r = reinterpret_cast<float*>(ws + L.t2r);
   float* buf[2] = {reinterpret_cast<float*>(ws + L.lbuf0), reinterpret_cast<float*>(ws + L.lbuf1)};
   float* rbuf[2] = {reinterpret_cast<float*>(ws + L.rbuf0), reinterpret_cast<float*>(ws + L.rbuf1)};
+  float* skl = reinterpret_cast<float*>(ws + L.sk);
+  float* skr = reinterpret_cast<float*>(ws + L.skr);
 
   // left site k: L_k -> T1 -> (MPO step) T2 -> L_{k+1}
   auto left_site = [&](int k, tn_tensor& cur, hipStream_t s) -> int32_t {
+    SplitKScope slices(skl, L.sk_floats);
     const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
     tn_tensor T1 = make_view(t1, TN_F32, {da, wl, d, db});
     tn_tensor T2 = make_view(t2, TN_F32, {da, d, wr, db});
@@ -749,6 +761,7 @@ int32_t tn_mps_env_sweep(int32_t n_sites, const tn_tensor* psi, const tn_tensor*
   };
   // right site k: R_{k+1} -> T1' -> (MPO step) T2' -> R_k
   auto right_site = [&](int k, tn_tensor& cur, hipStream_t s) -> int32_t {
+    SplitKScope slices(skr, L.sk_floats);
     const int64_t da = dims[k], db = dims[k + 1], wl = w[k], wr = w[k + 1];
     tn_tensor T1 = make_view(t1r, TN_F32, {da, d, db, wr});
     tn_tensor T2 = make_view(t2r, TN_F32, {wl, da, d, db});

@@ -329,6 +329,46 @@ def test_env_sweep_tuned_shared_chip(prec, tmp_path):
     assert torch.equal(e, e2)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_env_sweep_k_slices(prec, tmp_path):
+    """The sweep's GEMMs cut into 2 and into 4 k-slices (tile-cache entries
+    rewritten with the slice count: choice = tile + 100 log2(slices), loaded
+    at level 0 so nothing is re-timed) give environments within the oracle
+    tolerance; with two slices, which every bulk GEMM of this chain can
+    take, the sums run in another order than the whole GEMMs' (the results
+    differ from theirs in low bits).  Slice counts a GEMM cannot take (K too
+    short) fall back to the whole GEMM."""
+    n, chi = 16, 128   # bonds 1, 2, 4, ..., 128, 128, 128, ..., 2, 1
+    psi = canonical(n, chi, 227)
+    mpo = inputs.xxz_mpo(n, 0.5)
+    ls_ref, rs_ref, el, er = oracle.env_sweep(psi, mpo)
+    gp, gm = g32(psi), g32(mpo)
+    path = tmp_path / "tiles.txt"
+    outs = {}
+    try:
+        tn.tune(path, 1)
+        tn.mps_env_sweep(gp, gm, prec=prec)   # fills the cache
+        torch.cuda.synchronize()
+        lines = [x for x in path.read_text().splitlines() if x and not x.startswith("G ")]
+        assert lines
+        for lg in (0, 1, 2):
+            forced = tmp_path / f"tiles{lg}.txt"
+            forced.write_text("".join(
+                f"{x.split('->')[0].strip()} -> {int(x.split('->')[1]) % 100 + 100 * lg}\n" for x in lines))
+            tn.tune(forced, 0)
+            outs[lg] = tn.mps_env_sweep(gp, gm, prec=prec)
+            torch.cuda.synchronize()
+    finally:
+        tn.tune(None, 0)
+    for lg, (ls, rs, e) in outs.items():
+        errl, errr = env_errors(ls, rs, ls_ref, rs_ref)
+        assert errl <= TOL[prec] and errr <= TOL[prec], (lg, errl, errr)
+        sl, sr = energy_abs_scale(psi, mpo, ls_ref, rs_ref)
+        e = e.cpu().numpy()
+        assert abs(e[0] - el) <= TOL[prec] * sl and abs(e[1] - er) <= TOL[prec] * sr, (lg, e, el, er)
+    assert any(not torch.equal(outs[1][0][k], outs[0][0][k]) for k in range(1, n))
+
+
 def test_env_sweep_cfg2_full():
     """N = 100, chi = 256, TFIM (J = g = 1), canonical random MPS: FP32 vs the oracle."""
     n, chi = 100, 256
