@@ -151,14 +151,15 @@ static int choice_lg(int v) { return v / 100; }
 constexpr int kMaxSliceLg = 2;
 
 // Whether the GEMM can run as 2^lg k-slices into the scratch: one merged
-// contracted axis (a slice is a pointer offset), no batch, no per-batch
-// scale or |C| maximum, slices of whole 16-k steps and at least 64 long,
-// and room for the 2^lg dense M x N partial results.
+// contracted axis (a slice is a pointer offset), no batch (the scale and
+// |C| maximum, if any, are the single entry's and move to the sum kernel),
+// slices of whole 16-k steps and at least 64 long, and room for the 2^lg
+// dense M x N partial results.
 static bool slices_ok(const GemmDesc& d, int lg) {
   if (lg == 0) return true;
   const int S = 1 << lg;
-  return g_splitk && d.batch == 1 && d.gk.n == 1 && !d.a_scale_bits && !d.c_absmax && d.K % (16 * S) == 0 &&
-         d.K / S >= 64 && (size_t)S * (size_t)d.M * (size_t)d.N <= g_splitk_floats;
+  return g_splitk && d.batch == 1 && d.gk.n == 1 && d.K % (16 * S) == 0 && d.K / S >= 64 &&
+         (size_t)S * (size_t)d.M * (size_t)d.N <= g_splitk_floats;
 }
 
 // The slices as a batch of S GEMMs: slice z contracts k in [z K/S, (z+1) K/S)
@@ -175,6 +176,8 @@ static GemmDesc slice_desc(const GemmDesc& d, int S) {
   x.b_bs = (int64_t)Ks * d.gk.s[1][0];
   x.c = g_splitk;
   x.c_bs = (int64_t)d.M * d.N;
+  x.a_scale_bits = nullptr;   // applied to the sum (an exact power of two)
+  x.c_absmax = nullptr;       // taken over the sum
   int64_t st = d.N;
   for (int i = x.gm.n - 1; i >= 0; --i) {
     x.gm.s[1][i] = st;
@@ -190,19 +193,31 @@ static GemmDesc slice_desc(const GemmDesc& d, int S) {
 }
 
 // C[m, n] = the partials' sum over the slices in slice order (deterministic),
-// stored through C's index groups
+// times the GEMM's 2^-e scale if it has one, stored through C's index groups;
+// the GEMM's |C| maximum (if any) is taken over these values
 __global__ void __launch_bounds__(256) slice_sum_kernel(const float* __restrict__ part, int S, int M, int N,
-                                                        float* __restrict__ c, const Group gm, const Group gn) {
+                                                        float* __restrict__ c, const Group gm, const Group gn,
+                                                        const uint32_t* __restrict__ scale_bits,
+                                                        uint32_t* __restrict__ absmax) {
   const int64_t MN = (int64_t)M * N;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= MN) return;
-  const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
-  float s = part[i];
-  for (int z = 1; z < S; ++z) s += part[z * MN + i];
-  int64_t om[1], on[1];
-  group_offsets<1>(gm, (uint32_t)m, om, 1);
-  group_offsets<1>(gn, (uint32_t)n, on, 1);
-  c[om[0] + on[0]] = s;
+  float a = 0.f;
+  if (i < MN) {
+    const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
+    float s = part[i];
+    for (int z = 1; z < S; ++z) s += part[z * MN + i];
+    if (scale_bits) s *= pow2_inverse_scale(scale_bits[0]);
+    int64_t om[1], on[1];
+    group_offsets<1>(gm, (uint32_t)m, om, 1);
+    group_offsets<1>(gn, (uint32_t)n, on, 1);
+    c[om[0] + on[0]] = s;
+    a = fabsf(s);
+  }
+  if (absmax) {   // uniform over the grid: every lane reaches the shuffles
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) a = fmaxf(a, __shfl_xor(a, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(absmax, __float_as_uint(a));
+  }
 }
 
 static int heuristic_cfg(const GemmDesc& d, int prec) {
@@ -374,7 +389,7 @@ static int32_t launch_choice(GemmDesc& d, int32_t prec, int v, hipStream_t st) {
   TN_TRY(launch_gemm_cfg(x, prec, cfg, st));
   const int64_t MN = (int64_t)d.M * d.N;
   hipLaunchKernelGGL(slice_sum_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, g_splitk, S, d.M, d.N,
-                     d.c, d.gm, d.gn);
+                     d.c, d.gm, d.gn, d.a_scale_bits, d.c_absmax);
   return hip_check(hipGetLastError(), "k-slice sum");
 }
 

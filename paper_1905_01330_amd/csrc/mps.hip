@@ -124,7 +124,9 @@ static int32_t check_chain(int32_t n_sites, const tn_tensor* sites, const char* 
 //   T[a', s, b] = sum_a E[a', a] phi[a, s, b]        (E scaled by 2^-e of slot k)
 //   E'[b', b]  = sum_{a', s} psi[a', s, b'] T[a', s, b]
 static int32_t inner_site(const tn_tensor& psi, const tn_tensor& phi, float* e_in, float* e_out, float* t,
-                          uint32_t* slots, int k, int32_t prec, hipStream_t st) {
+                          uint32_t* slots, int k, int32_t prec, hipStream_t st, float* sk = nullptr,
+                          size_t sk_floats = 0) {
+  SplitKScope slices(sk, sk_floats);
   const int64_t da = psi.shape[0], db = phi.shape[0], d = psi.shape[1];
   const int64_t da2 = psi.shape[2], db2 = phi.shape[2];
   tn_tensor e = make_view(e_in, TN_F32, {da, db});
@@ -146,7 +148,9 @@ static int32_t inner_site(const tn_tensor& psi, const tn_tensor& phi, float* e_i
 //                                                      exact, so which factor carries it is immaterial)
 //   E_R'[a', a] = sum_{s, b} T[a', s, b] phi[a, s, b]
 static int32_t inner_site_right(const tn_tensor& psi, const tn_tensor& phi, float* e_in, float* e_out, float* t,
-                                uint32_t* in_slot, uint32_t* out_slot, int32_t prec, hipStream_t st) {
+                                uint32_t* in_slot, uint32_t* out_slot, int32_t prec, hipStream_t st,
+                                float* sk = nullptr, size_t sk_floats = 0) {
+  SplitKScope slices(sk, sk_floats);
   const int64_t da = psi.shape[0], db = phi.shape[0], d = psi.shape[1];
   const int64_t da2 = psi.shape[2], db2 = phi.shape[2];
   tn_tensor e = make_view(e_in, TN_F32, {da2, db2});
@@ -168,7 +172,8 @@ constexpr int kInnerTwoSided = 4;
 constexpr int kEnvDotParts = 256;
 
 struct InnerLayout {
-  size_t e0, e1, t, slots, er0, er1, tr, rslots, part, total;
+  size_t e0, e1, t, slots, er0, er1, tr, rslots, part, sk, skr, total;
+  size_t sk_floats;   // k-slice partials per end
 };
 
 static InnerLayout inner_layout(int32_t n, const std::vector<int64_t>& dp, const std::vector<int64_t>& dq, int64_t d) {
@@ -185,7 +190,12 @@ static InnerLayout inner_layout(int32_t n, const std::vector<int64_t>& dp, const
   L.tr = L.er1 + align256(me * 4);
   L.rslots = L.tr + align256(mt * 4);
   L.part = L.rslots + align256((size_t)(n + 1) * 4);
-  L.total = L.part + align256(kEnvDotParts * 8);
+  // k-slice scratch per end: four partial results of the largest
+  // intermediate, at most 8 Mi floats
+  L.sk_floats = (size_t)std::min<int64_t>(4 * std::max(mt, me), 1ll << 23);
+  L.sk = L.part + align256(kEnvDotParts * 8);
+  L.skr = L.sk + align256(L.sk_floats * 4);
+  L.total = L.skr + align256(L.sk_floats * 4);
   return L;
 }
 
@@ -616,10 +626,13 @@ int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi
   float* e[2] = {reinterpret_cast<float*>(ws + L.e0), reinterpret_cast<float*>(ws + L.e1)};
   float* t = reinterpret_cast<float*>(ws + L.t);
   uint32_t* slots = reinterpret_cast<uint32_t*>(ws + L.slots);
+  float* sk = reinterpret_cast<float*>(ws + L.sk);
+  float* skr = reinterpret_cast<float*>(ws + L.skr);
   if (n_sites < kInnerTwoSided) {
     hipLaunchKernelGGL(mps_init_kernel, dim3(grid_for(n_sites + 1)), dim3(256), 0, st, e[0], slots, n_sites + 1);
     TN_TRY(hip_check(hipGetLastError(), "mps init"));
-    for (int k = 0; k < n_sites; ++k) TN_TRY(inner_site(psi[k], phi[k], e[k & 1], e[(k + 1) & 1], t, slots, k, prec, st));
+    for (int k = 0; k < n_sites; ++k)
+      TN_TRY(inner_site(psi[k], phi[k], e[k & 1], e[(k + 1) & 1], t, slots, k, prec, st, sk, L.sk_floats));
     hipLaunchKernelGGL(mps_finish_kernel, dim3(1), dim3(256), 0, st, e[n_sites & 1], slots, n_sites, out2);
     return hip_check(hipGetLastError(), "mps finish");
   }
@@ -649,10 +662,11 @@ int32_t tn_mps_inner(int32_t n_sites, const tn_tensor* psi, const tn_tensor* phi
   {
     SharedChipScope shared;
     for (int i = 0; i < std::max(c, nr) && rc == TN_OK; ++i) {
-      if (i < c) rc = inner_site(psi[i], phi[i], e[i & 1], e[(i + 1) & 1], t, slots, i, prec, st);
+      if (i < c) rc = inner_site(psi[i], phi[i], e[i & 1], e[(i + 1) & 1], t, slots, i, prec, st, sk, L.sk_floats);
       if (rc == TN_OK && i < nr) {
         const int k = n_sites - 1 - i;
-        rc = inner_site_right(psi[k], phi[k], er[i & 1], er[(i + 1) & 1], tr, rslots + i, rslots + i + 1, prec, rs);
+        rc = inner_site_right(psi[k], phi[k], er[i & 1], er[(i + 1) & 1], tr, rslots + i, rslots + i + 1, prec, rs,
+                              skr, L.sk_floats);
       }
     }
   }

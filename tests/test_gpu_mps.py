@@ -64,6 +64,39 @@ def test_inner_correlated_pair(prec):
     assert value_rel(m, s, mr, sr) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_inner_k_slices(prec, tmp_path):
+    """The two-ended inner product's GEMMs cut into 2 and into 4 k-slices
+    (tile-cache entries rewritten with the slice count, loaded at level 0):
+    the ket-site GEMM's 2^-e scale and the bra-site GEMM's |C| maximum move
+    to the kernel that adds the slices.  On a chain whose raw value is far
+    beyond FP32 (so every step's rescaling matters) the values match the
+    oracle, and two slices change the result's low bits (the path ran)."""
+    psi, phi = inputs.correlated_mps_pair(40, 2, 128, 409)
+    psi, phi = [x * 32.0 for x in r32(psi)], r32(phi)
+    mr, sr = oracle.mps_inner(psi, phi)
+    assert sr > 88.0
+    gp, gq = g32(psi), g32(phi)
+    path = tmp_path / "tiles.txt"
+    got = {}
+    try:
+        tn.tune(path, 1)
+        ms(tn.mps_inner(gp, gq, prec=prec))   # fills the cache
+        lines = [x for x in path.read_text().splitlines() if x and not x.startswith("G ")]
+        assert lines
+        for lg in (0, 1, 2):
+            forced = tmp_path / f"tiles{lg}.txt"
+            forced.write_text("".join(
+                f"{x.split('->')[0].strip()} -> {int(x.split('->')[1]) % 100 + 100 * lg}\n" for x in lines))
+            tn.tune(forced, 0)
+            got[lg] = ms(tn.mps_inner(gp, gq, prec=prec))
+    finally:
+        tn.tune(None, 0)
+    for lg, (m, s) in got.items():
+        assert value_rel(m, s, mr, sr) <= TOL[prec], (lg, m, s, mr, sr)
+    assert got[1] != got[0]
+
+
 def test_inner_rescaling_over_long_chain():
     # entries 4x larger than normalised: the raw value would overflow FP32 by far
     psi = [x * 4.0 for x in r32(inputs.random_mps(200, 2, 32, 9))]
