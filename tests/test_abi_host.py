@@ -221,8 +221,10 @@ def test_tune_levels_and_cache_file(tmp_path):
     assert lib.tn_tune(None, -1) == -1
     assert lib.tn_tune(str(tmp_path / "no" / "such" / "dir" / "c.txt").encode(), 1) == -6
     path = tmp_path / "tiles.txt"
-    # a cache with one valid entry, one out-of-range tile and a malformed line
-    path.write_text("384 320 256 1 1 2 1 2 111 -> 3\n1 2 3 4 5 6 7 8 9 -> 999\nnot a line\n")
+    # a cache with valid entries (a whole GEMM, a tile in two k-slices), an
+    # out-of-range tile, an out-of-range slice count and a malformed line
+    path.write_text("384 320 256 1 1 2 1 2 111 -> 3\n256 768 512 1 1 1 0 2 1111 -> 114\n"
+                    "1 2 3 4 5 6 7 8 9 -> 999\n1 2 3 4 5 6 7 8 9 -> 314\nnot a line\n")
     assert lib.tn_tune(str(path).encode(), 2) == 0
     assert path.read_text().startswith("384 320 256")   # loading never rewrites the file
     assert lib.tn_tune(None, 0) == 0
