@@ -125,7 +125,8 @@ static bool cfg_allowed(const GemmDesc& d, int prec, int c) {
 }
 
 // set while the calling thread issues GEMMs that share the chip with a
-// concurrent stream (the two halves of a two-directional sweep)
+// concurrent stream (the two directions of a sweep, the two ends of an
+// inner product)
 static thread_local bool g_shared = false;
 
 SharedChipScope::SharedChipScope(bool on) : prev(g_shared) { g_shared = prev || on; }
