@@ -63,6 +63,16 @@ static int gemm_variant(const GemmDesc& d) {
 // it is k-contiguous, else one element per lane along k (lanes along n).
 static bool split_ok(const GemmDesc& d, int prec) {
   if (prec != TN_PREC_SPLIT_BF16 || d.gk.n != 1 || d.a_mode != LOAD_KVEC || d.K % 8 != 0) return false;
+  // their 16-byte buffer loads (A, and B when read along k) take 16-byte
+  // aligned rows
+  auto aligned = [](const void* p, const Group& rows, int64_t bs) {
+    if (reinterpret_cast<uintptr_t>(p) % 16 || bs % 4) return false;
+    for (int i = 0; i < rows.n; ++i)
+      if (rows.s[0][i] % 4) return false;
+    return true;
+  };
+  if (!aligned(d.a, d.gm, d.a_bs)) return false;
+  if (d.b_mode == LOAD_KVEC && !aligned(d.b, d.gn, d.b_bs)) return false;
   auto extent = [](const Group& g, int t) {
     int64_t e = 0;
     for (int i = 0; i < g.n; ++i) e += (int64_t)(g.dim[i] - 1) * g.s[t][i];
@@ -541,13 +551,8 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
 
 // the gather modes the grouped kernel derives for problem p (the same rules)
 int grouped_variant(const Gemm2D& p) {
-  auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
-  const int am = (p.sak == 1 && p.K % 4 == 0 && p.sam % 4 == 0 && al(p.a)) ? LOAD_KVEC
-               : (p.sam == 1 && p.M % 4 == 0 && p.sak % 4 == 0 && al(p.a)) ? LOAD_MNVEC
-                                                                            : LOAD_GENERIC;
-  const int bm = (p.sbk == 1 && p.K % 4 == 0 && p.sbn % 4 == 0 && al(p.b)) ? LOAD_KVEC
-               : (p.sbn == 1 && p.N % 4 == 0 && p.sbk % 4 == 0 && al(p.b)) ? LOAD_MNVEC
-                                                                            : LOAD_GENERIC;
+  const int am = p.sak == 1 ? LOAD_KVEC : (p.sam == 1 && p.M % 4 == 0) ? LOAD_MNVEC : LOAD_GENERIC;
+  const int bm = p.sbk == 1 ? LOAD_KVEC : (p.sbn == 1 && p.N % 4 == 0) ? LOAD_MNVEC : LOAD_GENERIC;
   if (am == LOAD_GENERIC || bm == LOAD_GENERIC) return 0;
   return 1 + (am == LOAD_MNVEC ? 2 : 0) + (bm == LOAD_MNVEC ? 1 : 0);
 }

@@ -86,14 +86,16 @@ __global__ void __launch_bounds__(WM* WN * WK * 64)
     one(d.gn, p.N, p.sbn, p.scn);
     one(d.gk, p.K, p.sak, p.sbk);
     auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
-    d.a_mode = (p.sak == 1 && p.K % 4 == 0 && p.sam % 4 == 0 && al(p.a)) ? LOAD_KVEC
-             : (p.sam == 1 && p.M % 4 == 0 && p.sak % 4 == 0 && al(p.a)) ? LOAD_MNVEC
-             : p.sam == 1                                                  ? LOAD_MNSCALAR
-                                                                          : LOAD_GENERIC;
-    d.b_mode = (p.sbk == 1 && p.K % 4 == 0 && p.sbn % 4 == 0 && al(p.b)) ? LOAD_KVEC
-             : (p.sbn == 1 && p.N % 4 == 0 && p.sbk % 4 == 0 && al(p.b)) ? LOAD_MNVEC
-             : p.sbn == 1                                                  ? LOAD_MNSCALAR
-                                                                          : LOAD_GENERIC;
+    // the gather modes of the plan's rules (16-byte loads need 4-byte
+    // alignment only; one contracted axis takes a partial last block)
+    d.a_mode = p.sak == 1                    ? LOAD_KVEC
+             : (p.sam == 1 && p.M % 4 == 0) ? LOAD_MNVEC
+             : p.sam == 1                    ? LOAD_MNSCALAR
+                                             : LOAD_GENERIC;
+    d.b_mode = p.sbk == 1                    ? LOAD_KVEC
+             : (p.sbn == 1 && p.N % 4 == 0) ? LOAD_MNVEC
+             : p.sbn == 1                    ? LOAD_MNSCALAR
+                                             : LOAD_GENERIC;
     d.c_mode = (p.scm == 1 && p.M % 4 == 0 && p.scn % 4 == 0 && al(p.c)) ? STORE_MVEC : STORE_SCALAR;
   }
   __syncthreads();

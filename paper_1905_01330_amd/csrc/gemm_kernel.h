@@ -21,6 +21,12 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+// the same with only 4-byte alignment: gfx950 runs 16-byte global loads at
+// any 4-byte-aligned address, so a row of an odd-sized operand that starts
+// anywhere is still read with one load per four elements
+typedef float f32x4u_t __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ __forceinline__ f32x4_t load4u(const float* p) { return *reinterpret_cast<const f32x4u_t*>(p); }
 
 enum Prec : int { P_FP32 = 0, P_BF16 = 1, P_X6 = 2, P_X3 = 3 };
 
@@ -239,7 +245,18 @@ struct OperandLoader {
         int idx = tid + v * NT;
         int k = k0 + (idx % KQ) * 4;
         f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-        if (((rowok >> v) & 1u) && k < K) x = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k));
+        if (((rowok >> v) & 1u) && k < K) {
+          // a partial last micro-block (K % 4 != 0, one contracted axis)
+          // is read element by element
+          const float* p = base + rowoff[v] + koff(gk, k);
+          if (k + 4 <= K) {
+            x = load4u(p);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              if (k + j < K) x[j] = p[j];
+          }
+        }
         st[v] = x;
       }
     } else if ((mode == LOAD_MNSCALAR || mode == LOAD_GENERIC) && gk.n == 1) {
@@ -308,15 +325,15 @@ struct OperandLoader {
         f32x4_t x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0, x2 = x0, x3 = x0;
         if (run) {
           const float* p = base + rowoff[v] + ko;
-          if (ok && k + 0 < K) x0 = *reinterpret_cast<const f32x4_t*>(p);
-          if (ok && k + 1 < K) x1 = *reinterpret_cast<const f32x4_t*>(p + ks);
-          if (ok && k + 2 < K) x2 = *reinterpret_cast<const f32x4_t*>(p + 2 * ks);
-          if (ok && k + 3 < K) x3 = *reinterpret_cast<const f32x4_t*>(p + 3 * ks);
+          if (ok && k + 0 < K) x0 = load4u(p);
+          if (ok && k + 1 < K) x1 = load4u(p + ks);
+          if (ok && k + 2 < K) x2 = load4u(p + 2 * ks);
+          if (ok && k + 3 < K) x3 = load4u(p + 3 * ks);
         } else {
-          if (ok && k + 0 < K) x0 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 0));
-          if (ok && k + 1 < K) x1 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 1));
-          if (ok && k + 2 < K) x2 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 2));
-          if (ok && k + 3 < K) x3 = *reinterpret_cast<const f32x4_t*>(base + rowoff[v] + koff(gk, k + 3));
+          if (ok && k + 0 < K) x0 = load4u(base + rowoff[v] + koff(gk, k + 0));
+          if (ok && k + 1 < K) x1 = load4u(base + rowoff[v] + koff(gk, k + 1));
+          if (ok && k + 2 < K) x2 = load4u(base + rowoff[v] + koff(gk, k + 2));
+          if (ok && k + 3 < K) x3 = load4u(base + rowoff[v] + koff(gk, k + 3));
         }
         st[4 * v + 0] = x0;
         st[4 * v + 1] = x1;
@@ -424,13 +441,26 @@ struct FastLoader {
   __device__ __forceinline__ void load_slot(int k0, int v) {
     if constexpr (MODE == LOAD_KVEC) {
       f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-      if (!TAIL || k0 + kq[v] < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v]);
+      if constexpr (!TAIL) {
+        x = load4u(ptr[v]);
+      } else {
+        // the stage's micro-blocks past K are zero; a partial one (K % 4
+        // != 0) is read element by element
+        const int k = k0 + kq[v];
+        if (k + 4 <= K) {
+          x = load4u(ptr[v]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            if (k + j < K) x[j] = ptr[v][j];
+        }
+      }
       st[SET][v] = x;
     } else {
 #pragma unroll
       for (int j = 0; j < KD; ++j) {
         f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-        if (!TAIL || k0 + kq[v] + j < K) x = *reinterpret_cast<const f32x4_t*>(ptr[v] + j * sk);
+        if (!TAIL || k0 + kq[v] + j < K) x = load4u(ptr[v] + j * sk);
         st[SET][KD * v + j] = x;
       }
     }

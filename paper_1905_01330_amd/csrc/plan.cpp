@@ -172,6 +172,19 @@ static int64_t group_size(const Group& g) {
 }
 
 // can operand `t` (stride index `ti`) be read as aligned float4 runs along group `inner`
+// 16-byte gathers along the unit-stride axis of `inner`.  The loads need
+// only 4-byte alignment (gfx950 runs global vector loads unaligned), so only
+// the run structure matters: every micro-block of four stays inside one run
+// of the innermost axis, or, for the contracted index with a single axis
+// (tail_ok), a partial last micro-block is read element by element.
+static bool vec4_load_ok(const Group& inner, int ti, bool tail_ok) {
+  if (inner.n < 1) return false;
+  const int last = inner.n - 1;
+  if (inner.s[ti][last] != 1) return false;
+  return inner.dim[last] % 4 == 0 || (tail_ok && inner.n == 1);
+}
+
+// 16-byte stores of four consecutive rows of C: aligned runs of four
 static bool vec4_ok(const Group& inner, int ti, const Group& other, int oi, const void* ptr, int64_t bstride) {
   if (inner.n < 1) return false;
   const int last = inner.n - 1;
@@ -191,12 +204,12 @@ static bool mn_scalar_ok(const Group& rows, int ti) {
 }
 
 void choose_modes(GemmDesc& d) {
-  d.a_mode = vec4_ok(d.gk, 0, d.gm, 0, d.a, d.a_bs) ? LOAD_KVEC
-           : vec4_ok(d.gm, 0, d.gk, 0, d.a, d.a_bs) ? LOAD_MNVEC
+  d.a_mode = vec4_load_ok(d.gk, 0, true)  ? LOAD_KVEC
+           : vec4_load_ok(d.gm, 0, false) ? LOAD_MNVEC
            : mn_scalar_ok(d.gm, 0)                   ? LOAD_MNSCALAR
                                                      : LOAD_GENERIC;
-  d.b_mode = vec4_ok(d.gk, 1, d.gn, 0, d.b, d.b_bs) ? LOAD_KVEC
-           : vec4_ok(d.gn, 0, d.gk, 1, d.b, d.b_bs) ? LOAD_MNVEC
+  d.b_mode = vec4_load_ok(d.gk, 1, true)  ? LOAD_KVEC
+           : vec4_load_ok(d.gn, 0, false) ? LOAD_MNVEC
            : mn_scalar_ok(d.gn, 0)                   ? LOAD_MNSCALAR
                                                      : LOAD_GENERIC;
   d.c_mode = vec4_ok(d.gm, 1, d.gn, 1, d.c, d.c_bs) ? STORE_MVEC : STORE_SCALAR;

@@ -159,6 +159,34 @@ def test_ragged_gemm_all_tiles(prec):
         tn.tune_force_config(-1)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_k_contiguous_operands_of_odd_extent_all_tiles(prec):
+    """A and B both read along k (unit stride) with K odd or small and rows
+    that start anywhere (a one-float offset into the buffer, odd row
+    pitches): 16-byte loads at 4-byte alignment and an element-by-element
+    partial last micro-block, on every tile configuration."""
+    rng = np.random.default_rng(29)
+    try:
+        for M, K, N in [(197, 301, 163), (70, 3, 45), (33, 5, 64), (40, 130, 36)]:
+            a = f32(rng.standard_normal((M, K)))
+            b = f32(rng.standard_normal((K, N)))
+            abuf = gpu(np.zeros(M * K + 1, dtype=np.float32))
+            ga = abuf[1:].view(M, K)
+            ga.copy_(gpu(a))
+            bbuf = gpu(np.zeros(N * K + 1, dtype=np.float32))
+            gbt = bbuf[1:].view(N, K)
+            gbt.copy_(gpu(b.T.copy()))
+            gb = gbt.t()                                  # B[k, n], k unit-stride
+            ref = a.astype(np.float64) @ b.astype(np.float64)
+            scale = np.abs(a).astype(np.float64) @ np.abs(b).astype(np.float64)
+            for cfg in range(tn.tune_num_configs()):
+                tn.tune_force_config(cfg)
+                out = tn.contract_between(ga, gb, [1], [0], prec=prec)
+                check(host(out), ref, scale, TOL[prec], f"{M}x{K}x{N} tile config {cfg}")
+    finally:
+        tn.tune_force_config(-1)
+
+
 # the last six tile configurations are the lean-stage split-BF16 kernels
 # (both operands through LDS; B private per wave; B private in two k
 # groups), then the same three on the exchanged operands
