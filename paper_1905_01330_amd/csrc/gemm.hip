@@ -53,6 +53,10 @@ static int gemm_variant(const GemmDesc& d) {
   if (d.gk.n != 1 || d.a_mode == LOAD_GENERIC || d.b_mode == LOAD_GENERIC || d.a_mode == LOAD_MNSCALAR ||
       d.b_mode == LOAD_MNSCALAR)
     return 0;
+  // the fast m/n-contiguous gathers read whole blocks of four rows; a
+  // partial last block is read by the run-time gathers
+  auto whole = [](const Group& g) { return g.dim[g.n - 1] % 4 == 0; };
+  if ((d.a_mode == LOAD_MNVEC && !whole(d.gm)) || (d.b_mode == LOAD_MNVEC && !whole(d.gn))) return 0;
   return 1 + (d.a_mode == LOAD_MNVEC ? 2 : 0) + (d.b_mode == LOAD_MNVEC ? 1 : 0);
 }
 
@@ -551,6 +555,7 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
 
 // the gather modes the grouped kernel derives for problem p (the same rules)
 int grouped_variant(const Gemm2D& p) {
+  // the fast m/n-contiguous gathers read whole blocks of four rows
   const int am = p.sak == 1 ? LOAD_KVEC : (p.sam == 1 && p.M % 4 == 0) ? LOAD_MNVEC : LOAD_GENERIC;
   const int bm = p.sbk == 1 ? LOAD_KVEC : (p.sbn == 1 && p.N % 4 == 0) ? LOAD_MNVEC : LOAD_GENERIC;
   if (am == LOAD_GENERIC || bm == LOAD_GENERIC) return 0;

@@ -87,15 +87,9 @@ __global__ void __launch_bounds__(WM* WN * WK * 64)
     one(d.gk, p.K, p.sak, p.sbk);
     auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
     // the gather modes of the plan's rules (16-byte loads need 4-byte
-    // alignment only; one contracted axis takes a partial last block)
-    d.a_mode = p.sak == 1                    ? LOAD_KVEC
-             : (p.sam == 1 && p.M % 4 == 0) ? LOAD_MNVEC
-             : p.sam == 1                    ? LOAD_MNSCALAR
-                                             : LOAD_GENERIC;
-    d.b_mode = p.sbk == 1                    ? LOAD_KVEC
-             : (p.sbn == 1 && p.N % 4 == 0) ? LOAD_MNVEC
-             : p.sbn == 1                    ? LOAD_MNSCALAR
-                                             : LOAD_GENERIC;
+    // alignment only; single axes take a partial last block)
+    d.a_mode = p.sak == 1 ? LOAD_KVEC : p.sam == 1 ? LOAD_MNVEC : LOAD_GENERIC;
+    d.b_mode = p.sbk == 1 ? LOAD_KVEC : p.sbn == 1 ? LOAD_MNVEC : LOAD_GENERIC;
     d.c_mode = (p.scm == 1 && p.M % 4 == 0 && p.scn % 4 == 0 && al(p.c)) ? STORE_MVEC : STORE_SCALAR;
   }
   __syncthreads();

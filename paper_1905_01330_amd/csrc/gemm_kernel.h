@@ -323,7 +323,24 @@ struct OperandLoader {
         const int64_t ks = gk.s[KIDX][last];
         const bool ok = (rowok >> v) & 1u;
         f32x4_t x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0, x2 = x0, x3 = x0;
-        if (run) {
+        // a partial last block of rows (one row axis, M % 4 != 0): element by
+        // element, rows past the end read as zero
+        const int nv = nrows - (row0 + (idx / KQ) * 4);
+        if (ok && nv < 4) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (k + j >= K) continue;
+            const float* p = base + rowoff[v] + koff(gk, k + j);
+            f32x4_t y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+              if (i < nv) y[i] = p[i];
+            if (j == 0) x0 = y;
+            else if (j == 1) x1 = y;
+            else if (j == 2) x2 = y;
+            else x3 = y;
+          }
+        } else if (run) {
           const float* p = base + rowoff[v] + ko;
           if (ok && k + 0 < K) x0 = load4u(p);
           if (ok && k + 1 < K) x1 = load4u(p + ks);
@@ -419,6 +436,9 @@ struct FastLoader {
         // distinct banks while its global reads stay 128-byte runs per k row
         row = row0 + (idx / KQ) * 4;
         k = (idx % KQ) * KD;
+        // whole blocks of four rows (the fast gathers take M % 4 == 0); a
+        // block past the end re-reads the last one (its LDS rows are past M
+        // and never stored)
         row = row < nrows ? row : nrows - 4;
       }
       int64_t o[1];

@@ -175,8 +175,8 @@ static int64_t group_size(const Group& g) {
 // 16-byte gathers along the unit-stride axis of `inner`.  The loads need
 // only 4-byte alignment (gfx950 runs global vector loads unaligned), so only
 // the run structure matters: every micro-block of four stays inside one run
-// of the innermost axis, or, for the contracted index with a single axis
-// (tail_ok), a partial last micro-block is read element by element.
+// of the innermost axis, or, for an index with a single axis (tail_ok), a
+// partial last micro-block is read element by element.
 static bool vec4_load_ok(const Group& inner, int ti, bool tail_ok) {
   if (inner.n < 1) return false;
   const int last = inner.n - 1;
@@ -204,12 +204,12 @@ static bool mn_scalar_ok(const Group& rows, int ti) {
 }
 
 void choose_modes(GemmDesc& d) {
-  d.a_mode = vec4_load_ok(d.gk, 0, true)  ? LOAD_KVEC
-           : vec4_load_ok(d.gm, 0, false) ? LOAD_MNVEC
+  d.a_mode = vec4_load_ok(d.gk, 0, true) ? LOAD_KVEC
+           : vec4_load_ok(d.gm, 0, true) ? LOAD_MNVEC
            : mn_scalar_ok(d.gm, 0)                   ? LOAD_MNSCALAR
                                                      : LOAD_GENERIC;
-  d.b_mode = vec4_load_ok(d.gk, 1, true)  ? LOAD_KVEC
-           : vec4_load_ok(d.gn, 0, false) ? LOAD_MNVEC
+  d.b_mode = vec4_load_ok(d.gk, 1, true) ? LOAD_KVEC
+           : vec4_load_ok(d.gn, 0, true) ? LOAD_MNVEC
            : mn_scalar_ok(d.gn, 0)                   ? LOAD_MNSCALAR
                                                      : LOAD_GENERIC;
   d.c_mode = vec4_ok(d.gm, 1, d.gn, 1, d.c, d.c_bs) ? STORE_MVEC : STORE_SCALAR;

@@ -160,11 +160,12 @@ def test_ragged_gemm_all_tiles(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_k_contiguous_operands_of_odd_extent_all_tiles(prec):
+def test_operands_of_odd_extent_all_tiles(prec):
     """A and B both read along k (unit stride) with K odd or small and rows
     that start anywhere (a one-float offset into the buffer, odd row
-    pitches): 16-byte loads at 4-byte alignment and an element-by-element
-    partial last micro-block, on every tile configuration."""
+    pitches), then both row-contiguous with M and N odd: 16-byte loads at
+    4-byte alignment and an element-by-element partial last block, on
+    every tile configuration."""
     rng = np.random.default_rng(29)
     try:
         for M, K, N in [(197, 301, 163), (70, 3, 45), (33, 5, 64), (40, 130, 36)]:
@@ -183,6 +184,19 @@ def test_k_contiguous_operands_of_odd_extent_all_tiles(prec):
                 tn.tune_force_config(cfg)
                 out = tn.contract_between(ga, gb, [1], [0], prec=prec)
                 check(host(out), ref, scale, TOL[prec], f"{M}x{K}x{N} tile config {cfg}")
+            # the same operands stored row-contiguous (M and N unit-stride,
+            # odd extents, rows from a one-float offset): 16-byte loads of
+            # four rows with an element-wise partial last block
+            at = gpu(np.zeros(K * M + 1, dtype=np.float32))
+            gat = at[1:].view(K, M)
+            gat.copy_(gpu(a.T.copy()))
+            bb = gpu(np.zeros(K * N + 1, dtype=np.float32))
+            gbb = bb[1:].view(K, N)
+            gbb.copy_(gpu(b))
+            for cfg in range(tn.tune_num_configs()):
+                tn.tune_force_config(cfg)
+                out = tn.contract_between(gat.t(), gbb, [1], [0], prec=prec)
+                check(host(out), ref, scale, TOL[prec], f"{M}x{K}x{N} row-contiguous, tile config {cfg}")
     finally:
         tn.tune_force_config(-1)
 
