@@ -53,10 +53,14 @@ static int gemm_variant(const GemmDesc& d) {
   if (d.gk.n != 1 || d.a_mode == LOAD_GENERIC || d.b_mode == LOAD_GENERIC || d.a_mode == LOAD_MNSCALAR ||
       d.b_mode == LOAD_MNSCALAR)
     return 0;
-  // the fast m/n-contiguous gathers read whole blocks of four rows; a
-  // partial last block is read by the run-time gathers
-  auto whole = [](const Group& g) { return g.dim[g.n - 1] % 4 == 0; };
-  if ((d.a_mode == LOAD_MNVEC && !whole(d.gm)) || (d.b_mode == LOAD_MNVEC && !whole(d.gn))) return 0;
+  // the fast m/n-contiguous gathers read blocks of four rows; a partial last
+  // block (one row axis, M % 4 != 0) needs M >= 4 and a k stride >= 4,
+  // since the stages before the last may read up to three elements past it
+  auto fits = [](const Group& g, int64_t sk) {
+    return g.dim[g.n - 1] % 4 == 0 || (g.n == 1 && g.dim[0] >= 4 && sk >= 4);
+  };
+  if ((d.a_mode == LOAD_MNVEC && !fits(d.gm, d.gk.s[0][0])) || (d.b_mode == LOAD_MNVEC && !fits(d.gn, d.gk.s[1][0])))
+    return 0;
   return 1 + (d.a_mode == LOAD_MNVEC ? 2 : 0) + (d.b_mode == LOAD_MNVEC ? 1 : 0);
 }
 
@@ -555,9 +559,11 @@ int32_t launch_gemm(GemmDesc& d, int32_t prec, hipStream_t st) {
 
 // the gather modes the grouped kernel derives for problem p (the same rules)
 int grouped_variant(const Gemm2D& p) {
-  // the fast m/n-contiguous gathers read whole blocks of four rows
-  const int am = p.sak == 1 ? LOAD_KVEC : (p.sam == 1 && p.M % 4 == 0) ? LOAD_MNVEC : LOAD_GENERIC;
-  const int bm = p.sbk == 1 ? LOAD_KVEC : (p.sbn == 1 && p.N % 4 == 0) ? LOAD_MNVEC : LOAD_GENERIC;
+  // the fast m/n-contiguous gathers: whole blocks of four rows, or a partial
+  // last one with M >= 4 and a k stride >= 4
+  auto fits = [](int m, int64_t sk) { return m % 4 == 0 || (m >= 4 && sk >= 4); };
+  const int am = p.sak == 1 ? LOAD_KVEC : (p.sam == 1 && fits(p.M, p.sak)) ? LOAD_MNVEC : LOAD_GENERIC;
+  const int bm = p.sbk == 1 ? LOAD_KVEC : (p.sbn == 1 && fits(p.N, p.sbk)) ? LOAD_MNVEC : LOAD_GENERIC;
   if (am == LOAD_GENERIC || bm == LOAD_GENERIC) return 0;
   return 1 + (am == LOAD_MNVEC ? 2 : 0) + (bm == LOAD_MNVEC ? 1 : 0);
 }

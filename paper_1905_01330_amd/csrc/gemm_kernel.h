@@ -417,10 +417,13 @@ struct FastLoader {
   int kq[NV];
   int64_t sk;
   int K;
+  int row0, nrows;
 
-  __device__ __forceinline__ void init(const float* base, const Group& grows, int row0, int nrows, int64_t sk_, int K_) {
+  __device__ __forceinline__ void init(const float* base, const Group& grows, int row0_, int nrows_, int64_t sk_, int K_) {
     sk = sk_;
     K = K_;
+    row0 = row0_;
+    nrows = nrows_;
     const int tid = threadIdx.x;
     (void)tid;
 #pragma unroll
@@ -436,9 +439,8 @@ struct FastLoader {
         // distinct banks while its global reads stay 128-byte runs per k row
         row = row0 + (idx / KQ) * 4;
         k = (idx % KQ) * KD;
-        // whole blocks of four rows (the fast gathers take M % 4 == 0); a
-        // block past the end re-reads the last one (its LDS rows are past M
-        // and never stored)
+        // a block past the end re-reads the last whole one (its LDS rows
+        // are past M and never stored); M >= 4
         row = row < nrows ? row : nrows - 4;
       }
       int64_t o[1];
@@ -480,7 +482,22 @@ struct FastLoader {
 #pragma unroll
       for (int j = 0; j < KD; ++j) {
         f32x4_t x = {0.f, 0.f, 0.f, 0.f};
-        if (!TAIL || k0 + kq[v] + j < K) x = load4u(ptr[v] + j * sk);
+        if constexpr (!TAIL) {
+          // a partial last block of rows (M % 4 != 0) reads up to three
+          // elements past row M - 1 of this k: inside the view, since no
+          // stage but the last holds k = K - 1 and the k stride is >= 4
+          x = load4u(ptr[v] + j * sk);
+        } else if (k0 + kq[v] + j < K) {
+          // the last stage reads a partial block element by element
+          const int nv = nrows - (row0 + (block_of(v) / KQ) * 4);
+          if (nv >= 4 || nv <= 0) {
+            x = load4u(ptr[v] + j * sk);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+              if (i < nv) x[i] = ptr[v][j * sk + i];
+          }
+        }
         st[SET][KD * v + j] = x;
       }
     }
@@ -493,12 +510,13 @@ struct FastLoader {
     for (int v = 0; v < NV; ++v) load_slot<TAIL, SET>(k0, v);
   }
 
-  // load stage kt (k0 = kt * BK) into register set SET, if the stage exists
+  // stage kt (k0 = kt * BK) into register set SET, if the stage exists;
+  // the last stage (partial or not) takes the careful loads
   template <int SET>
-  __device__ __forceinline__ void load_stage(int kt, int nfull, int nk) {
-    if (kt < nfull)
+  __device__ __forceinline__ void load_stage(int kt, int nk) {
+    if (kt < nk - 1)
       load<false, SET>(kt * BK);
-    else if (kt < nk)
+    else if (kt == nk - 1)
       load<true, SET>(kt * BK);
   }
 
@@ -902,7 +920,6 @@ struct GemmTile {
       FastLoader<P, BN, BK, NT, BMODE, DEPTH> lb;
       la.init(d.a + bz * d.a_bs, d.gm, m0, d.M, d.gk.s[0][0], d.K);
       lb.init(d.b + bz * d.b_bs, d.gn, n0, d.N, d.gk.s[1][0], d.K);
-      const int nfull = d.K / BK;
       using LA = FastLoader<P, BM, BK, NT, AMODE, DEPTH>;
       using LB = FastLoader<P, BN, BK, NT, BMODE, DEPTH>;
       constexpr int NVA = LA::NV, NVB = LB::NV;
@@ -912,18 +929,18 @@ struct GemmTile {
       // (set = stage parity when DEPTH = 2; with one set it is refilled right
       // after its stage is stored); while stage kt's MFMAs run, stage kt+1
       // is split and stored into the other LDS buffer.  One barrier per stage.
-      la.template load_stage<0>(0, nfull, nk);
-      lb.template load_stage<0>(0, nfull, nk);
+      la.template load_stage<0>(0, nk);
+      lb.template load_stage<0>(0, nk);
       if constexpr (DEPTH == 2) {
-        la.template load_stage<1>(1, nfull, nk);
-        lb.template load_stage<1>(1, nfull, nk);
+        la.template load_stage<1>(1, nk);
+        lb.template load_stage<1>(1, nk);
       }
       la.template store<0>(smem);
       lb.template store<0>(smem + bytesA);
       if constexpr (DEPTH == 1) {
         // one register set: it is refilled as soon as its stage is stored
-        la.template load_stage<0>(1, nfull, nk);
-        lb.template load_stage<0>(1, nfull, nk);
+        la.template load_stage<0>(1, nk);
+        lb.template load_stage<0>(1, nk);
       }
       __syncthreads();
       static_assert(FLUSH % 2 == 0 || FLUSH == 1, "stage groups must keep the register-set parity static");
@@ -935,7 +952,8 @@ struct GemmTile {
       // stages on and stores the next one, so a stage is one straight-line
       // block that the scheduler can interleave (loads, split, LDS traffic
       // and MFMAs)
-      for (; kt0 + G - 1 + AHEAD < nfull; kt0 += G) {
+      // (the last stage, which holds k = K - 1, is loaded in the tail loop)
+      for (; kt0 + G - 1 + AHEAD < nk - 1; kt0 += G) {
 #pragma unroll
         for (int s = 0; s < G; ++s) {
           const int kt = kt0 + s;
@@ -1010,13 +1028,13 @@ struct GemmTile {
                   la.template store<0>(nxt);
                   lb.template store<0>(nxt + bytesA);
                 }
-                la.template load_stage<0>(kt + 2, nfull, nk);
-                lb.template load_stage<0>(kt + 2, nfull, nk);
+                la.template load_stage<0>(kt + 2, nk);
+                lb.template load_stage<0>(kt + 2, nk);
               };
               compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
             } else if (s & 1) {
-              la.template load_stage<1>(kt + 2, nfull, nk);
-              lb.template load_stage<1>(kt + 2, nfull, nk);
+              la.template load_stage<1>(kt + 2, nk);
+              lb.template load_stage<1>(kt + 2, nk);
               auto st_next = [&](int part) {
                 if (part == 0 && kt + 1 < nk) {
                   la.template store<0>(nxt);
@@ -1025,8 +1043,8 @@ struct GemmTile {
               };
               compute(cur, cur + bytesA, acc, tmp, first, flush, wm_off, wn_off, kslice, st_next);
             } else {
-              la.template load_stage<0>(kt + 2, nfull, nk);
-              lb.template load_stage<0>(kt + 2, nfull, nk);
+              la.template load_stage<0>(kt + 2, nk);
+              lb.template load_stage<0>(kt + 2, nk);
               auto st_next = [&](int part) {
                 if (part == 0 && kt + 1 < nk) {
                   la.template store<1>(nxt);
