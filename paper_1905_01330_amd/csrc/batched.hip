@@ -1,11 +1,13 @@
 // Uneven batch of MPS inner products in one call.  Chains of four or more
 // sites are contracted from both ends at once (sites 0 .. c-1 from the left,
 // n-1 .. c from the right, c = n / 2), so the number of steps is half the
-// longest chain.  Every step is two grouped GEMM launches (ket site into the
-// environments, then the bra site) over the left and right halves still
-// active, with the problems of a launch described by a compact table in the
-// workspace, largest first so the longest tiles start earliest.  At the end
-// each chain's two environments meet in an FP64 sum over its middle bond.
+// longest chain.  The right halves run on the caller's stream and the left
+// halves on a side stream.  On each, every step is two grouped GEMM launches
+// (ket site into the environments, then the bra site) over the halves still
+// active (one per gather variant when their layouts differ), with the
+// problems of a launch described by a compact table in the workspace,
+// largest first so the longest tiles start earliest.  At the end each
+// chain's two environments meet in an FP64 sum over its middle bond.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -98,6 +100,7 @@ struct Launch {
   int32_t tiles[kGroupedCfgs];       // per grouped tile: workgroups of the launch
   int heur;                          // the tile the work estimate picks
   int variant;                       // gather variant shared by every problem of the launch
+  int side;                          // 0: the caller's stream (right halves), 1: the side stream (left halves)
   uint64_t sig;                      // the step's problems (shapes and variant), for the tile cache
 };
 
@@ -119,7 +122,7 @@ bool is_contiguous(const tn_tensor& t) {
 }
 
 // Work estimate of the tile for one site step, shared by all of its problems
-// (one launch per step and product); used when tuning is off or the stream
+// (one launch per step, product and half); used when tuning is off or the stream
 // is being captured.  With tuning on, the first launch of each step
 // signature and precision times the four grouped tiles instead.  A step is usually too small to fill the chip with
 // 128 x 128 tiles, so its time is the latency of one tile rather than the
@@ -163,6 +166,8 @@ int step_cfg(const std::vector<Gemm2D>& v) {
   }
   return best;
 }
+
+static int32_t add_launch(BatchPlan& P, std::vector<std::pair<int64_t, Gemm2D>>& u, int var, int side);
 
 int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const tn_tensor* phi, char* ws,
               BatchPlan& P) {
@@ -238,7 +243,7 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
   P.chain_bytes = o;
   for (int j = 0; j < max_steps; ++j) {
     for (int g = 0; g < 2; ++g) {
-      std::vector<std::pair<int64_t, Gemm2D>> v;
+      std::vector<std::pair<int64_t, Gemm2D>> v, vl;   // right halves, left halves
       for (int c = 0; c < n_chains; ++c) {
         const ChainRec& r = P.chains[c];
         if (j >= r.n - r.c) continue;
@@ -317,58 +322,73 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
           q.scn = 1;
           q.c_absmax = r.slots + j + 1;
         }
-        v.push_back({(int64_t)q.M * q.N * q.K, q});
+        vl.push_back({(int64_t)q.M * q.N * q.K, q});
       }
-      if (v.empty()) continue;
-      // one launch per step and product (more launches would only serialise
-      // it): the fast gathers when every problem allows the same variant,
-      // else the run-time gathers; the largest problems take the first tiles
-      int var = grouped_variant(v[0].second);
-      for (auto& e : v)
-        if (grouped_variant(e.second) != var) var = 0;
-      std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
-      std::vector<Gemm2D> qs;
-      for (auto& e : v) qs.push_back(e.second);
-      Launch L;
-      L.prob_off = P.probs.size();
-      L.n_probs = (int32_t)v.size();
-      L.heur = step_cfg(qs);
-      L.variant = var;
-      // FNV-1a over the problem shapes in launch order and the variant
-      uint64_t h = 1469598103934665603ull;
-      auto mix = [&h](uint64_t x) {
-        for (int b = 0; b < 8; ++b) {
-          h ^= (x >> (8 * b)) & 0xffu;
-          h *= 1099511628211ull;
+      // The right halves run on the caller's stream and the left halves on
+      // a side stream, each half's steps in order; the halves are
+      // independent until the final sums.  The two halves' products have
+      // different layouts (a step's left bra product reads both operands
+      // along their rows), so each launch holds one half and one gather
+      // variant: the fast gathers for every problem of it; the largest
+      // problems take the first tiles.
+      for (int side = 0; side < 2; ++side)
+        for (int var = 0; var <= 4; ++var) {
+          std::vector<std::pair<int64_t, Gemm2D>> u;
+          for (auto& e : side == 0 ? v : vl)
+            if (grouped_variant(e.second) == var) u.push_back(e);
+          if (u.empty()) continue;
+          TN_TRY(add_launch(P, u, var, side));
         }
-      };
-      mix((uint64_t)var);
-      for (const Gemm2D& q : qs) {
-        mix((uint64_t)q.M);
-        mix((uint64_t)q.N);
-        mix((uint64_t)q.K);
-        P.probs.push_back(q);
-      }
-      L.sig = h;
-      // a tile-start table for every grouped tile, so the tile can be chosen per launch
-      for (int g2 = 0; g2 < kGroupedCfgs; ++g2) {
-        const int tm = grouped_tile_m(g2), tn_ = grouped_tile_n(g2);
-        L.tile_off[g2] = P.tstart.size();
-        int64_t t = 0;
-        for (const Gemm2D& q : qs) {
-          P.tstart.push_back((int32_t)t);
-          t += (int64_t)((q.M + tm - 1) / tm) * ((q.N + tn_ - 1) / tn_);
-        }
-        if (t >= (1ll << 31)) return fail(TN_ERR_UNSUPPORTED, "too many tiles in one step");
-        L.tiles[g2] = (int32_t)t;
-      }
-      P.launches.push_back(L);
     }
   }
   P.chain_tab = align256b(P.chain_bytes);
   P.prob_tab = P.chain_tab + align256b(P.chains.size() * sizeof(ChainRec));
   P.tile_tab = P.prob_tab + align256b(P.probs.size() * sizeof(Gemm2D));
   P.total = P.tile_tab + align256b(P.tstart.size() * sizeof(int32_t));
+  return TN_OK;
+}
+
+// one grouped launch over problems u (one half, one gather variant)
+static int32_t add_launch(BatchPlan& P, std::vector<std::pair<int64_t, Gemm2D>>& u, int var, int side) {
+  std::stable_sort(u.begin(), u.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  std::vector<Gemm2D> qs;
+  for (auto& e : u) qs.push_back(e.second);
+  Launch L;
+  L.prob_off = P.probs.size();
+  L.n_probs = (int32_t)u.size();
+  L.heur = step_cfg(qs);
+  L.variant = var;
+  L.side = side;
+  // FNV-1a over the problem shapes in launch order, the variant and the half
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](uint64_t x) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (x >> (8 * b)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)var);
+  mix((uint64_t)side);
+  for (const Gemm2D& q : qs) {
+    mix((uint64_t)q.M);
+    mix((uint64_t)q.N);
+    mix((uint64_t)q.K);
+    P.probs.push_back(q);
+  }
+  L.sig = h;
+  // a tile-start table for every grouped tile, so the tile can be chosen per launch
+  for (int g2 = 0; g2 < kGroupedCfgs; ++g2) {
+    const int tm = grouped_tile_m(g2), tn_ = grouped_tile_n(g2);
+    L.tile_off[g2] = P.tstart.size();
+    int64_t t = 0;
+    for (const Gemm2D& q : qs) {
+      P.tstart.push_back((int32_t)t);
+      t += (int64_t)((q.M + tm - 1) / tm) * ((q.N + tn_ - 1) / tn_);
+    }
+    if (t >= (1ll << 31)) return fail(TN_ERR_UNSUPPORTED, "too many tiles in one step");
+    L.tiles[g2] = (int32_t)t;
+  }
+  P.launches.push_back(L);
   return TN_OK;
 }
 
@@ -430,12 +450,25 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   TN_TRY(hip_check(hipGetLastError(), "batched init"));
   const int forced = forced_grouped_cfg();
   const int level = forced >= 0 ? 0 : tune_timing_level(st);
-  auto run = [&](const Launch& L, int cfg) {
+  // the left halves on a side stream forked from `stream` after the init
+  // and joined back before the sums (capturable)
+  hipStream_t ls = st;
+  TN_TRY(side_stream(ls));
+  hipEvent_t fork = nullptr, join = nullptr;
+  TN_TRY(hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "create event"));
+  if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+    hipEventDestroy(fork);
+    return fail(TN_ERR_DEVICE, "create event failed");
+  }
+  hipEventRecord(fork, st);
+  hipStreamWaitEvent(ls, fork, 0);
+  auto run = [&](const Launch& L, int cfg, hipStream_t s) {
     return launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off[cfg], L.n_probs, L.tiles[cfg], prec, cfg,
-                               L.variant, st);
+                               L.variant, s);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  for (const Launch& L : Q.launches) {
+  auto issue = [&](const Launch& L) -> int32_t {
+    const hipStream_t s = L.side ? ls : st;
     int cfg = forced >= 0 ? forced : grouped_tune_get(L.sig, prec);
     if (cfg < 0) {
       bool timed = false;
@@ -451,10 +484,10 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
         float best = 1e30f;
         const int reps = level >= 2 ? 10 : 3;
         for (int c = 0; c < kGroupedCfgs; ++c) {
-          TN_TRY(run(L, c));
-          TN_TRY(hip_check(hipEventRecord(e0, st), "tuning event"));
-          for (int r = 0; r < reps; ++r) TN_TRY(run(L, c));
-          TN_TRY(hip_check(hipEventRecord(e1, st), "tuning event"));
+          TN_TRY(run(L, c, s));
+          TN_TRY(hip_check(hipEventRecord(e0, s), "tuning event"));
+          for (int r = 0; r < reps; ++r) TN_TRY(run(L, c, s));
+          TN_TRY(hip_check(hipEventRecord(e1, s), "tuning event"));
           TN_TRY(hip_check(hipEventSynchronize(e1), "tuning event"));
           float ms = 0.f;
           TN_TRY(hip_check(hipEventElapsedTime(&ms, e0, e1), "tuning event"));
@@ -467,10 +500,20 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
       }
       grouped_tune_put(L.sig, prec, cfg, timed);
     }
-    TN_TRY(run(L, cfg));
+    return run(L, cfg, s);
+  };
+  int32_t rc = TN_OK;
+  for (const Launch& L : Q.launches) {
+    rc = issue(L);
+    if (rc != TN_OK) break;
   }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
+  hipEventRecord(join, ls);
+  hipStreamWaitEvent(st, join, 0);
+  hipEventDestroy(fork);
+  hipEventDestroy(join);
+  TN_TRY(rc);
   hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(kFinishThreads), 0, st, d_chains, n_chains, out2);
   return hip_check(hipGetLastError(), "batched finish");
 }
