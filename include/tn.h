@@ -422,7 +422,7 @@ int32_t tn_dmrg_eigensolve(const tn_tensor* L, const tn_tensor* R, const tn_tens
  *          signature, time every candidate tile 3 times and keep the fastest;
  *       2: the same with 10 timed launches per candidate (less noise).
  * The uneven batched inner product is tuned the same way per site step:
- * the first launch of each (step signature, precision) times its four
+ * the first launch of each (step signature, precision) times its
  * grouped tiles, re-running the step on its real inputs, and keeps the
  * fastest.
  * The GEMMs of a two-direction environment sweep and of a two-ended inner
@@ -477,11 +477,12 @@ int32_t tn_tune_num_configs(void);
 int32_t tn_measure_split_mfma_rate(int32_t n_steps, int32_t zero_operands, float* out, void* stream);
 
 /* Pin the tile of every site step of the uneven batched inner product:
- * 0: 128 x 128, 1: 64 x 64, 2: 32 x 32, 3: 64 x 64 in two k-slices; -1
- * restores the per-step choice (tuned or estimated).  The upload writes the
- * tile tables of all four tiles, so the setting may change between an
- * upload and its launches.  Meant for measurement and tests.
- * TN_ERR_INVALID_ARGUMENT outside -1 .. 3. */
+ * 0: 128 x 128, 1: 64 x 64, 2: 32 x 32, 3: 64 x 64 in two k-slices,
+ * 4: 160 x 256 on eight waves (launches whose problems need the run-time
+ * gathers take 0 instead); -1 restores the per-step choice (tuned or
+ * estimated).  The upload writes the tile tables of all five tiles, so the
+ * setting may change between an upload and its launches.  Meant for
+ * measurement and tests.  TN_ERR_INVALID_ARGUMENT outside -1 .. 4. */
 int32_t tn_tune_force_grouped_config(int32_t cfg);
 
 #ifdef __cplusplus

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kFinishThreads) batched_finish_kernel(const Ch
 
 namespace {
 
-constexpr int kGroupedCfgs = 4;
+constexpr int kGroupedCfgs = 5;   // the last (160 x 256, eight waves) for fast-gather launches only
 
 struct Launch {
   size_t prob_off;                   // index into the problem table
@@ -124,7 +124,7 @@ bool is_contiguous(const tn_tensor& t) {
 // Work estimate of the tile for one site step, shared by all of its problems
 // (one launch per step, product and half); used when tuning is off or the stream
 // is being captured.  With tuning on, the first launch of each step
-// signature and precision times the four grouped tiles instead.  A step is usually too small to fill the chip with
+// signature and precision times the grouped tiles instead.  A step is usually too small to fill the chip with
 // 128 x 128 tiles, so its time is the latency of one tile rather than the
 // total work: the estimate is, in units of one wave's 32 x 32 block times one
 // k, the larger of the longest wave's work and the total padded work spread
@@ -469,7 +469,10 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto issue = [&](const Launch& L) -> int32_t {
     const hipStream_t s = L.side ? ls : st;
-    int cfg = forced >= 0 ? forced : grouped_tune_get(L.sig, prec);
+    // the eight-wave tile serves fast-gather launches only
+    const int ncfg = L.variant ? kGroupedCfgs : kGroupedCfgs - 1;
+    int cfg = forced >= 0 ? (forced < ncfg ? forced : 0) : grouped_tune_get(L.sig, prec);
+    if (cfg >= ncfg) cfg = 0;
     if (cfg < 0) {
       bool timed = false;
       cfg = L.heur;
@@ -483,7 +486,7 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
         }
         float best = 1e30f;
         const int reps = level >= 2 ? 10 : 3;
-        for (int c = 0; c < kGroupedCfgs; ++c) {
+        for (int c = 0; c < ncfg; ++c) {
           TN_TRY(run(L, c, s));
           TN_TRY(hip_check(hipEventRecord(e0, s), "tuning event"));
           for (int r = 0; r < reps; ++r) TN_TRY(run(L, c, s));

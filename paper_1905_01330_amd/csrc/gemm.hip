@@ -122,7 +122,7 @@ static GemmFn pick_fn(const GemmDesc& d, int prec, int cfg, bool lean) {
 }
 
 // grouped configurations: 0 -> 128x128, 1 -> 64x64, 2 -> 32x32, 3 -> 64x64 in two k-slices
-static const int kGroupedCfg[4] = {3, 15, 7, 14};
+static const int kGroupedCfg[5] = {3, 15, 7, 14, 10};
 int grouped_tile_m(int cfg) { return kCfgs[kGroupedCfg[cfg]].bm; }
 int grouped_tile_n(int cfg) { return kCfgs[kGroupedCfg[cfg]].bn; }
 
@@ -292,7 +292,7 @@ static void load_cache_file_locked() {
     if (line[0] == 'G') {
       unsigned long long sig = 0;
       int pr = 0, c = -1;
-      if (std::sscanf(line, "G %llx %d -> %d", &sig, &pr, &c) == 3 && c >= 0 && c < 4)
+      if (std::sscanf(line, "G %llx %d -> %d", &sig, &pr, &c) == 3 && c >= 0 && c < 5)
         g_grouped_cache[std::make_pair((uint64_t)sig, pr)] = c;
       continue;
     }
@@ -620,7 +620,7 @@ int32_t tn_tune_force_config(int32_t cfg) {
 int32_t tn_tune_num_configs(void) { return tn::kNumCfgs; }
 
 int32_t tn_tune_force_grouped_config(int32_t cfg) {
-  if (cfg < -1 || cfg > 3) return tn::fail(TN_ERR_INVALID_ARGUMENT, "grouped tile config %d", cfg);
+  if (cfg < -1 || cfg > 4) return tn::fail(TN_ERR_INVALID_ARGUMENT, "grouped tile config %d", cfg);
   tn::g_forced_grouped.store(cfg);
   return TN_OK;
 }

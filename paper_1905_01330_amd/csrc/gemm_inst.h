@@ -140,6 +140,11 @@ GroupedFn grouped_fn_modes(int cfg) {
     case 0: return gemm_grouped_kernel<P, 128, 128, 32, 2, 2, AM, BM_>;
     case 1: return gemm_grouped_kernel<P, 64, 64, 64, 2, 2, AM, BM_>;
     case 3: return gemm_grouped_kernel<P, 64, 64, 64, 2, 2, AM, BM_, 2>;
+    // eight waves side by side: fast gathers only (the run-time gathers
+    // exceed its register budget; such launches never take this tile)
+    case 4:
+      if constexpr (AM >= 0 && BM_ >= 0) return gemm_grouped_kernel<P, 160, 256, 32, 1, 8, AM, BM_>;
+      else return gemm_grouped_kernel<P, 128, 128, 32, 2, 2, AM, BM_>;
     default: return gemm_grouped_kernel<P, 32, 32, 32, 1, 1, AM, BM_>;
   }
 }

@@ -179,7 +179,7 @@ def test_tuner_controls():
     assert n >= 4
     assert lib.tn_tune_force_config(n) == -1
     assert lib.tn_tune_force_config(-1) == 0
-    assert lib.tn_tune_force_grouped_config(4) == -1
+    assert lib.tn_tune_force_grouped_config(5) == -1
     assert lib.tn_tune_force_grouped_config(-2) == -1
     assert lib.tn_tune_force_grouped_config(-1) == 0
     assert lib.tn_tune_set_level(5) == -1
