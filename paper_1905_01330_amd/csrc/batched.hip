@@ -1,13 +1,14 @@
 // Uneven batch of MPS inner products in one call.  Chains of four or more
 // sites are contracted from both ends at once (sites 0 .. c-1 from the left,
 // n-1 .. c from the right, c = n / 2), so the number of steps is half the
-// longest chain.  The right halves run on the caller's stream and the left
-// halves on a side stream.  On each, every step is two grouped GEMM launches
-// (ket site into the environments, then the bra site) over the halves still
-// active (one per gather variant when their layouts differ), with the
-// problems of a launch described by a compact table in the workspace,
-// largest first so the longest tiles start earliest.  At the end each
-// chain's two environments meet in an FP64 sum over its middle bond.
+// longest chain.  Every step is two grouped GEMM launches (ket site into the
+// environments, then the bra site) over the halves still active: for small
+// steps one launch per product over both halves, for larger ones one per
+// half and gather variant, the right halves on the caller's stream and the
+// left halves on a side stream.  The problems of a launch are described by a
+// compact table in the workspace, largest first so the longest tiles start
+// earliest.  At the end each chain's two environments meet in an FP64 sum
+// over its middle bond.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -92,6 +93,9 @@ __global__ void __launch_bounds__(kFinishThreads) batched_finish_kernel(const Ch
 namespace {
 
 constexpr int kGroupedCfgs = 5;   // the last (160 x 256, eight waves) for fast-gather launches only
+// a step whose problems have no extent above this runs both halves in one
+// launch per product (launch latency, not the gathers, sets its time)
+constexpr int kSmallStepExtent = 128;
 
 struct Launch {
   size_t prob_off;                   // index into the problem table
@@ -101,6 +105,7 @@ struct Launch {
   int heur;                          // the tile the work estimate picks
   int variant;                       // gather variant shared by every problem of the launch
   int side;                          // 0: the caller's stream (right halves), 1: the side stream (left halves)
+  bool has_left;                     // a caller's-stream launch that holds left halves too (small steps)
   uint64_t sig;                      // the step's problems (shapes and variant), for the tile cache
 };
 
@@ -167,7 +172,7 @@ int step_cfg(const std::vector<Gemm2D>& v) {
   return best;
 }
 
-static int32_t add_launch(BatchPlan& P, std::vector<std::pair<int64_t, Gemm2D>>& u, int var, int side);
+static int32_t add_launch(BatchPlan& P, std::vector<std::pair<int64_t, Gemm2D>>& u, int var, int side, bool has_left);
 
 int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const tn_tensor* phi, char* ws,
               BatchPlan& P) {
@@ -242,8 +247,10 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
   }
   P.chain_bytes = o;
   for (int j = 0; j < max_steps; ++j) {
+    std::vector<std::pair<int64_t, Gemm2D>> vs[2], vls[2];   // per product: right halves, left halves
     for (int g = 0; g < 2; ++g) {
-      std::vector<std::pair<int64_t, Gemm2D>> v, vl;   // right halves, left halves
+      std::vector<std::pair<int64_t, Gemm2D>>& v = vs[g];
+      std::vector<std::pair<int64_t, Gemm2D>>& vl = vls[g];
       for (int c = 0; c < n_chains; ++c) {
         const ChainRec& r = P.chains[c];
         if (j >= r.n - r.c) continue;
@@ -324,20 +331,39 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
         }
         vl.push_back({(int64_t)q.M * q.N * q.K, q});
       }
-      // The right halves run on the caller's stream and the left halves on
-      // a side stream, each half's steps in order; the halves are
-      // independent until the final sums.  The two halves' products have
-      // different layouts (a step's left bra product reads both operands
-      // along their rows), so each launch holds one half and one gather
-      // variant: the fast gathers for every problem of it; the largest
-      // problems take the first tiles.
+    }
+    // A step whose extents are all small is bound by launch latency: both
+    // halves go into one launch per product on the caller's stream (the
+    // run-time gathers when their layouts differ).  In a larger step the
+    // right halves run on the caller's stream and the left halves on a side
+    // stream, the halves being independent until the final sums; their
+    // products have different layouts (a left bra product reads both
+    // operands along their rows), so each launch holds one half and one
+    // gather variant and takes the fast gathers.  The largest problems of a
+    // launch take the first tiles.
+    bool small = true;
+    for (int g = 0; g < 2; ++g)
+      for (const auto* w : {&vs[g], &vls[g]})
+        for (const auto& e : *w)
+          if (std::max(e.second.M, std::max(e.second.N, e.second.K)) > kSmallStepExtent) small = false;
+    for (int g = 0; g < 2; ++g) {
+      if (small) {
+        std::vector<std::pair<int64_t, Gemm2D>> u = vs[g];
+        u.insert(u.end(), vls[g].begin(), vls[g].end());
+        if (u.empty()) continue;
+        int var = grouped_variant(u[0].second);
+        for (const auto& e : u)
+          if (grouped_variant(e.second) != var) var = 0;
+        TN_TRY(add_launch(P, u, var, 0, !vls[g].empty()));
+        continue;
+      }
       for (int side = 0; side < 2; ++side)
         for (int var = 0; var <= 4; ++var) {
           std::vector<std::pair<int64_t, Gemm2D>> u;
-          for (auto& e : side == 0 ? v : vl)
+          for (auto& e : side == 0 ? vs[g] : vls[g])
             if (grouped_variant(e.second) == var) u.push_back(e);
           if (u.empty()) continue;
-          TN_TRY(add_launch(P, u, var, side));
+          TN_TRY(add_launch(P, u, var, side, false));
         }
     }
   }
@@ -349,7 +375,7 @@ int32_t build(int32_t n_chains, const int32_t* off, const tn_tensor* psi, const 
 }
 
 // one grouped launch over problems u (one half, one gather variant)
-static int32_t add_launch(BatchPlan& P, std::vector<std::pair<int64_t, Gemm2D>>& u, int var, int side) {
+static int32_t add_launch(BatchPlan& P, std::vector<std::pair<int64_t, Gemm2D>>& u, int var, int side, bool has_left) {
   std::stable_sort(u.begin(), u.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
   std::vector<Gemm2D> qs;
   for (auto& e : u) qs.push_back(e.second);
@@ -359,6 +385,7 @@ static int32_t add_launch(BatchPlan& P, std::vector<std::pair<int64_t, Gemm2D>>&
   L.heur = step_cfg(qs);
   L.variant = var;
   L.side = side;
+  L.has_left = has_left;
   // FNV-1a over the problem shapes in launch order, the variant and the half
   uint64_t h = 1469598103934665603ull;
   auto mix = [&h](uint64_t x) {
@@ -450,18 +477,16 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   TN_TRY(hip_check(hipGetLastError(), "batched init"));
   const int forced = forced_grouped_cfg();
   const int level = forced >= 0 ? 0 : tune_timing_level(st);
-  // the left halves on a side stream forked from `stream` after the init
-  // and joined back before the sums (capturable)
+  // the left halves of the larger steps run on a side stream: the work
+  // moves to it (an event on `stream` it waits for) at the first such
+  // launch and back (an event on it that `stream` waits for) before a
+  // launch that holds left halves on `stream`, and before the sums
+  // (capturable)
   hipStream_t ls = st;
   TN_TRY(side_stream(ls));
-  hipEvent_t fork = nullptr, join = nullptr;
-  TN_TRY(hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "create event"));
-  if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
-    hipEventDestroy(fork);
-    return fail(TN_ERR_DEVICE, "create event failed");
-  }
-  hipEventRecord(fork, st);
-  hipStreamWaitEvent(ls, fork, 0);
+  hipEvent_t hop = nullptr;
+  TN_TRY(hip_check(hipEventCreateWithFlags(&hop, hipEventDisableTiming), "create event"));
+  bool left_on_side = false;
   auto run = [&](const Launch& L, int cfg, hipStream_t s) {
     return launch_gemm_grouped(d_probs + L.prob_off, d_tiles + L.tile_off[cfg], L.n_probs, L.tiles[cfg], prec, cfg,
                                L.variant, s);
@@ -507,15 +532,25 @@ int32_t tn_mps_inner_batched_launch(int32_t n_chains, const int32_t* site_offset
   };
   int32_t rc = TN_OK;
   for (const Launch& L : Q.launches) {
+    if (L.side == 1 && !left_on_side) {
+      hipEventRecord(hop, st);
+      hipStreamWaitEvent(ls, hop, 0);
+      left_on_side = true;
+    } else if (L.side == 0 && L.has_left && left_on_side) {
+      hipEventRecord(hop, ls);
+      hipStreamWaitEvent(st, hop, 0);
+      left_on_side = false;
+    }
     rc = issue(L);
     if (rc != TN_OK) break;
   }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
-  hipEventRecord(join, ls);
-  hipStreamWaitEvent(st, join, 0);
-  hipEventDestroy(fork);
-  hipEventDestroy(join);
+  if (left_on_side) {
+    hipEventRecord(hop, ls);
+    hipStreamWaitEvent(st, hop, 0);
+  }
+  hipEventDestroy(hop);
   TN_TRY(rc);
   hipLaunchKernelGGL(batched_finish_kernel, dim3(n_chains), dim3(kFinishThreads), 0, st, d_chains, n_chains, out2);
   return hip_check(hipGetLastError(), "batched finish");
