@@ -75,6 +75,14 @@ struct SplitKScope {
   float* prev_p;
   size_t prev_n;
 };
+// Householder QR of a column-major m x n FP64 matrix (m >= n, m <= 2048 when
+// householder_qr_fits): factorised in place, with the panels' triangular
+// factors in tf (householder_tf_doubles(n) doubles) and tau (n doubles);
+// householder_apply_q replaces y (m x ncols, column-major) by Q y.
+bool householder_qr_fits(int64_t m);
+size_t householder_tf_doubles(int64_t n);
+int32_t householder_qr(double* xc, int m, int n, double* tau, double* tf, hipStream_t st);
+int32_t householder_apply_q(const double* xc, int m, int n, const double* tf, double* y, int ncols, hipStream_t st);
 // K <= 32 with N or M <= 16 (and no batch, scale or max-abs): the HBM-bound path
 bool gemm_small_fits(const GemmDesc& d);
 int32_t launch_gemm_small(const GemmDesc& d, int32_t prec, hipStream_t st);

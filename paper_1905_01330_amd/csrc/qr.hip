@@ -474,6 +474,35 @@ static unsigned blocks_for(int64_t n) {
 
 // X, Q and T come in two sets, used by alternate sites: a site's Q is formed
 // on the side stream while the next site is factorised
+// Householder QR of a column-major m x n matrix (m >= n) for other callers:
+// the blocked path only (m <= 2048), factorised in place (R in the upper
+// triangle, the reflectors below), T factors in tf; and the product Q y.
+bool householder_qr_fits(int64_t m) { return m <= (int64_t)kQrThreads * kQrRows; }
+
+size_t householder_tf_doubles(int64_t n) { return (size_t)((n + kQrNb - 1) / kQrNb) * kQrNb * kQrNb; }
+
+int32_t householder_qr(double* xc, int m, int n, double* tau, double* tf, hipStream_t st) {
+  for (int j0 = 0; j0 < n; j0 += kQrNb) {
+    const int nb = std::min(kQrNb, n - j0);
+    hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(kQrThreads), 0, st, xc, tau, tf, m, j0, nb);
+    const int rest = n - j0 - nb;
+    if (rest > 0)
+      hipLaunchKernelGGL(qr_apply_kernel, dim3((unsigned)((rest + kQrCb - 1) / kQrCb)), dim3(kQrThreads), 0, st, xc, tf,
+                         xc, m, j0, nb, j0 + nb, rest, 1);
+  }
+  return hip_check(hipGetLastError(), "householder qr");
+}
+
+// y (m x ncols, column-major) := Q y, the panels applied last to first
+int32_t householder_apply_q(const double* xc, int m, int n, const double* tf, double* y, int ncols, hipStream_t st) {
+  for (int j0 = (n - 1) / kQrNb * kQrNb; j0 >= 0; j0 -= kQrNb) {
+    const int nb = std::min(kQrNb, n - j0);
+    hipLaunchKernelGGL(qr_apply_kernel, dim3((unsigned)((ncols + kQrCb - 1) / kQrCb)), dim3(kQrThreads), 0, st, xc, tf,
+                       y, m, j0, nb, 0, ncols, 0);
+  }
+  return hip_check(hipGetLastError(), "householder apply");
+}
+
 struct QrLayout {
   size_t x[2], q[2], r, tau, tf[2], total;
 };

@@ -132,6 +132,54 @@ def test_rank_deficient_and_degenerate():
     check_full(known_spectrum(30, 20, sdeg, 8), [0], [1], torch.float64, max_sv=5)
 
 
+def decompose_sweeps(ga, n_left):
+    """Jacobi sweeps the decomposition of ga (left legs first) takes, through the C-ABI."""
+    import ctypes as C
+    from paper_1905_01330_amd import _lib as L
+    da = L.tensor_desc(ga)
+    nbytes = C.c_size_t(0)
+    L.check(L.lib().tn_split_node_workspace(C.byref(da), n_left, C.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=DEV)
+    k, sweeps = C.c_int32(0), C.c_int32(0)
+    L.check(L.lib().tn_split_node_decompose(C.byref(da), n_left, -1, -1.0, C.byref(k), C.byref(sweeps),
+                                            C.c_void_p(ws.data_ptr()), nbytes.value, L.stream_ptr()))
+    return k.value, sweeps.value
+
+
+def test_preconditioned_sweeps_on_a_graded_spectrum():
+    """The sweeps run on R^T of a Householder QR: on the graded 1000 x 1000 node
+    (e^(-i/40)) they converge in far fewer sweeps than the 41 the node itself
+    takes, and the values stay those of the oracle."""
+    s = np.exp(-np.arange(1000) / 40.0)
+    ga = torch.tensor(known_spectrum(1000, 1000, s, 7), device=DEV)
+    k, sweeps = decompose_sweeps(ga, 1)
+    print("graded 1000 x 1000: sweeps", sweeps)
+    assert k == 1000 and sweeps <= 20
+
+
+def test_preconditioned_rank_deficient():
+    """Rank 3 in a 120 x 64 node and an all-zero 40 x 36 node (both wide enough
+    for the QR-preconditioned sweeps): zero values, zero vectors for them, no NaN."""
+    a = known_spectrum(120, 64, [3.0, 2.0, 1.0], 9)
+    check_full(a, [0], [1], torch.float64)
+    left, right, tr = tn.split_node(torch.tensor(a, device=DEV), [0], [1], max_truncation_err=1e-9)
+    assert left.shape[1] == 3 and tr.shape[0] == 61
+    np.testing.assert_allclose(host(left) @ host(right), a, atol=1e-12 * 3.0)
+    z = torch.zeros((40, 36), dtype=torch.float64, device=DEV)
+    u, sv, vt, tr = tn.split_node_full_svd(z, [0], [1])
+    for t in (u, sv, vt, tr):
+        assert torch.isfinite(t).all()
+    assert sv.numel() == 0 or float(sv.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("shape", [(2100, 40), (40, 2100), (2048, 48)])
+def test_long_side_at_and_past_the_qr_rows(shape):
+    """A long side of 2048 rows (the most the blocked QR takes) and past it,
+    where the sweeps run on the node itself."""
+    a = np.random.default_rng(shape[0]).standard_normal(shape)
+    check_full(a, [0], [1], torch.float64)
+
+
 def test_errors_before_launch():
     a = torch.zeros((4, 5), device=DEV, dtype=torch.float64)
     with pytest.raises(ValueError):
