@@ -21,10 +21,11 @@
 //   3. writes X back and replaces the same columns of V by V J.
 // Rotations taken from the current columns, not from an updated Gram
 // matrix, keep the small singular values accurate when a pair mixes large
-// and tiny columns.  KB is the widest of 8, 4, 2, 1 whose block pair fits in
-// LDS for the number of rows; beyond that (more than kMaxLdsRows rows) the
-// pair kernel forms the Gram matrix instead and diagonalises it in LDS
-// (accurate to eps times the largest singular value only).
+// and tiny columns.  KB is the one of 8, 4, 2, 1 with the cheapest modelled
+// sweep among those whose block pair fits in LDS for the number of rows;
+// when none fits (about 9600 rows) the pair kernel forms the Gram matrix
+// instead and diagonalises it in LDS (accurate to eps times the largest
+// singular value only).
 // Before every sweep the columns are ranked by norm and the blocks take them
 // in that order (a permutation table, no data moves): pairing columns of
 // similar size first cuts the sweeps needed on graded spectra by a third.
@@ -269,7 +270,15 @@ constexpr int kInnerLds = 1;         // sweeps over a block pair per visit
 
 // rows a block pair of 2 KB columns can hold in LDS (with its 2KB x 2KB J)
 constexpr int64_t lds_rows(int KB) { return (kLdsDoubles - 4 * KB * KB) / (2 * KB); }
-constexpr int64_t kMaxLdsRows = lds_rows(1);
+// LDS column length for R rows: a multiple of the rows one pass of a column
+// pair's threads covers (kNT / KB lanes, two rows each), zero past R
+constexpr int64_t lds_padded_rows(int64_t R, int KB) {
+  return (R + 2 * (kNT / KB) - 1) / (2 * (kNT / KB)) * (2 * (kNT / KB));
+}
+
+// Workgroup barrier for LDS data only: waits for this wave's LDS operations,
+// not for its global loads in flight (a __syncthreads fence waits for both)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int KB>
 __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, int64_t R, int64_t Cp, int nb,
@@ -279,23 +288,60 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
   __shared__ double lds[kLdsDoubles];
   __shared__ int any_rot;
   double* J = lds;                    // NC x NC, J[i * NC + j]
-  double* X = lds + NC * NC;          // column c at X + c * R
+  double* X = lds + NC * NC;          // column c at X + c * Rp (16-byte aligned)
+  const int Rp = (int)lds_padded_rows(R, KB);
+  const int NI = Rp / (2 * TPP);      // two-row loads per lane over a column
   const int tid = threadIdx.x;
+  // rows per thread per pass of the copies below: 32 loads in flight per
+  // thread before their values are used (one load at a time waits out the
+  // memory latency once per load)
+  constexpr int U = NC >= 16 ? 1 : 16 / NC;
   int p, q;
   round_pair(nb, round, blockIdx.x, p, q);
-  auto colof = [&](int c) { return perm[c < KB ? p * KB + c : q * KB + (c - KB)]; };
-  for (int64_t e = tid; e < (int64_t)NC * R; e += kNT) {
-    const int c = (int)(e / R);
-    X[e] = W[(int64_t)colof(c) * R + (e - (int64_t)c * R)];
+  int64_t col[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) col[c] = perm[c < KB ? p * KB + c : q * KB + (c - KB)];
+  // (loads past the last row read the last row again: no branch around them)
+  for (int64_t r0 = 0; r0 < Rp; r0 += (int64_t)U * kNT) {
+    double t[NC][U];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = r0 + u * kNT + tid;
+        t[c][u] = W[col[c] * R + (r < R ? r : R - 1)];
+      }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = r0 + u * kNT + tid;
+        if (r < Rp) X[c * Rp + r] = r < R ? t[c][u] : 0.0;
+      }
+  }
+  // the first U * kNT rows of the pair's V columns, loaded now: their latency
+  // overlaps the rotations (the barriers below wait for LDS only)
+  // (not for KB = 8, whose registers the rotations need)
+  constexpr bool kPrefetch = NC <= 8;
+  double vp[U][NC];
+  if constexpr (kPrefetch) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int64_t r = u * kNT + tid;
+        vp[u][c] = V[col[c] * Cp + (r < Cp ? r : Cp - 1)];
+      }
   }
   for (int e = tid; e < NC * NC; e += kNT) J[e] = (e / NC) == (e % NC) ? 1.0 : 0.0;
   if (tid == 0) any_rot = 0;
-  __syncthreads();
+  lds_barrier();
 
   const int pi = tid / TPP, lane = tid % TPP;   // column pair of the step, lane within it
   bool rotated_here = false;
   for (int sweep = 0; sweep < kInnerLds; ++sweep) {
     bool rot_sweep = false;
+#pragma unroll 1
     for (int step = 0; step < NC - 1; ++step) {
       // the step's pairs: the circle method on NC columns (NC = 2: one pair)
       int a, b;
@@ -314,14 +360,15 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
         a = b;
         b = t;
       }
-      const double* xa = X + (int64_t)a * R;
-      const double* xb = X + (int64_t)b * R;
+      const double2* xa = reinterpret_cast<const double2*>(X + a * Rp);
+      const double2* xb = reinterpret_cast<const double2*>(X + b * Rp);
       double al = 0.0, be = 0.0, ga = 0.0;
-      for (int64_t r = lane; r < R; r += TPP) {
-        const double u = xa[r], v = xb[r];
-        al += u * u;
-        be += v * v;
-        ga += u * v;
+#pragma unroll 4
+      for (int i = 0; i < NI; ++i) {
+        const double2 u = xa[i * TPP + lane], v = xb[i * TPP + lane];
+        al += u.x * u.x + u.y * u.y;
+        be += v.x * v.x + v.y * v.y;
+        ga += u.x * v.x + u.y * v.y;
       }
 #pragma unroll
       for (int o = TPP / 2; o >= 1; o >>= 1) {
@@ -339,7 +386,7 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
           part[wv][1] = be;
           part[wv][2] = ga;
         }
-        __syncthreads();
+        lds_barrier();
         const int w0 = (pi * TPP) / 64;
         al = be = ga = 0.0;
         for (int w = 0; w < TPP / 64; ++w) {
@@ -356,12 +403,13 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
         c = 1.0 / sqrt(1.0 + t * t);
         sn = t * c;
         rot_sweep = true;
-        double* wa = X + (int64_t)a * R;
-        double* wb = X + (int64_t)b * R;
-        for (int64_t r = lane; r < R; r += TPP) {
-          const double u = wa[r], v = wb[r];
-          wa[r] = c * u - sn * v;
-          wb[r] = sn * u + c * v;
+        double2* wa = reinterpret_cast<double2*>(X + a * Rp);
+        double2* wb = reinterpret_cast<double2*>(X + b * Rp);
+#pragma unroll 4
+        for (int i = 0; i < NI; ++i) {
+          const double2 u = wa[i * TPP + lane], v = wb[i * TPP + lane];
+          wa[i * TPP + lane] = make_double2(c * u.x - sn * v.x, c * u.y - sn * v.y);
+          wb[i * TPP + lane] = make_double2(sn * u.x + c * v.x, sn * u.y + c * v.y);
         }
         for (int i = lane; i < NC; i += TPP) {
           const double u = J[i * NC + a], v = J[i * NC + b];
@@ -369,39 +417,56 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
           J[i * NC + b] = sn * u + c * v;
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
     if (rot_sweep) any_rot = 1;
-    __syncthreads();
+    lds_barrier();
     const bool more = any_rot != 0;
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) any_rot = 0;
     if (!more) break;
     rotated_here = true;
-    __syncthreads();
+    lds_barrier();
   }
-  if (!rotated_here) return;   // already orthogonal: W and V unchanged
+  if (!rotated_here) {
+    // already orthogonal: W and V unchanged (the V loads still in flight are
+    // waited for before the wave ends)
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
   if (tid == 0) atomicAdd(rotated, 1);
-  for (int64_t e = tid; e < (int64_t)NC * R; e += kNT) {
-    const int c = (int)(e / R);
-    W[(int64_t)colof(c) * R + (e - (int64_t)c * R)] = X[e];
-  }
-  __syncthreads();
-  // V[:, cols] <- V[:, cols] J: one row per thread at a time, the row's NC
+  for (int c = 0; c < NC; ++c)
+    for (int64_t r = tid; r < R; r += kNT) W[col[c] * R + r] = X[c * Rp + r];
+  // V[:, cols] <- V[:, cols] J: U rows per thread at a time, each row's NC
   // values in registers, J read from LDS (every lane reads the same entry)
-  for (int64_t r = tid; r < Cp; r += kNT) {
-    double v[NC], o[NC];
+  for (int64_t r0 = 0; r0 < Cp; r0 += (int64_t)U * kNT) {
+    // J stays in LDS for KB = 8 (its 256 entries would take 512 registers
+    // if hoisted out of the loop)
+    if constexpr (NC >= 16) asm volatile("" ::: "memory");
+    double v[U][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) v[c] = V[(int64_t)colof(c) * Cp + r];
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double acc = 0.0;
+      for (int c = 0; c < NC; ++c) {
+        const int64_t r = r0 + u * kNT + tid;
+        v[u][c] = kPrefetch && r0 == 0 ? vp[u][c] : V[col[c] * Cp + (r < Cp ? r : Cp - 1)];
+      }
 #pragma unroll
-      for (int i = 0; i < NC; ++i) acc += v[i] * J[i * NC + c];
-      o[c] = acc;
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + u * kNT + tid;
+      double o[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) acc += v[u][i] * J[i * NC + c];
+        o[c] = acc;
+      }
+      if (r < Cp) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) V[col[c] * Cp + r] = o[c];
+      }
     }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) V[(int64_t)colof(c) * Cp + r] = o[c];
   }
 }
 
@@ -597,26 +662,28 @@ int32_t svd_geometry(const tn_tensor* a, int32_t n_left, SvdGeom& g) {
   if (g.C > 16384) return fail(TN_ERR_UNSUPPORTED, "the shorter effective leg (%lld) exceeds 16384", (long long)g.C);
   // Block width: a sweep is nb - 1 rounds (nb ~ C / KB), each one launch
   // whose pairs run side by side and whose work per pair grows like KB^2 R.
-  // Modelled sweep time: rounds x (5 us + 100 us x (KB / 8)^2 x R / 1000),
-  // measured for the pair kernel on gfx950; the cheapest width whose pair
-  // fits in LDS is taken.
+  // Modelled sweep time: rounds x (13 us + 0.72 us x KB^2 x R / 1000), plus
+  // 3 us a round for KB = 1 (its pair spans four wavefronts), fitted to the
+  // LDS kernel on gfx950 at R = 1000 (17, 16, 25 and 57 us a round for KB =
+  // 1, 2, 4, 8); the cheapest width whose pair fits in LDS is taken.
   // QR preconditioning (see the decompose call) runs the sweeps on a C x C
   // matrix instead of the R x C one
   g.precond = householder_qr_fits(g.R) && g.C >= kPrecondMinCols;
   const int64_t jr = g.precond ? g.C : g.R;   // rows of the swept matrix
   g.kb = kB;   // Gram-matrix pair kernel
   double best = INFINITY;
+  g.lds = false;
   for (int w : {8, 4, 2, 1}) {
-    if (jr > lds_rows(w)) continue;
+    if (lds_padded_rows(jr, w) > lds_rows(w)) continue;
+    g.lds = true;
     int nbw = (int)((g.C + w - 1) / w);
     nbw = nbw < 2 ? 2 : nbw + (nbw % 2);
-    const double t = (nbw - 1) * (5.0 + 100.0 * (w / 8.0) * (w / 8.0) * (double)jr / 1000.0);
+    const double t = (nbw - 1) * (13.0 + (w == 1 ? 3.0 : 0.0) + 0.72 * w * w * (double)jr / 1000.0);
     if (t < best) {
       best = t;
       g.kb = w;
     }
   }
-  g.lds = jr <= kMaxLdsRows;
   g.nb = (int)((g.C + g.kb - 1) / g.kb);
   if (g.nb < 2) g.nb = 2;
   if (g.nb % 2) g.nb += 1;
