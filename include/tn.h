@@ -148,9 +148,13 @@ int32_t tn_outer_product(const tn_tensor* a, const tn_tensor* b, tn_tensor* out,
  * Contracting a label between two nodes contracts every edge they share
  * (flattening).  Nodes still unconnected at the end are joined by outer
  * products in node order.  The final permutation is fused into the last
- * step's store.  Intermediates, and the scratch of the rank-0/1 sums (see
- * tn_contract_between), live in `workspace` (caller-owned);
- * tn_contract_network_workspace returns the bytes needed.
+ * step's store.  Intermediates, the scratch of the rank-0/1 sums (see
+ * tn_contract_between) and the partial results of k-sliced steps live in
+ * `workspace` (caller-owned); tn_contract_network_workspace returns the bytes
+ * needed.  A step whose result spans few tiles and whose contracted extent
+ * is long may run as up to 64 k-slices (one batched launch into partials,
+ * then a sum in slice order; the tile tuner times the slice counts); the
+ * partials take up to 64x the largest step's result, at most 16 MiB.
  * ------------------------------------------------------------------- */
 int32_t tn_contract_network_workspace(int32_t n_nodes, const tn_tensor* nodes,
                                       const int32_t* labels, const int32_t* offsets,
@@ -167,7 +171,8 @@ int32_t tn_contract_network(int32_t n_nodes, const tn_tensor* nodes, const int32
  * TN_NOALLOC_SCRATCH_BYTES per GPU (128 MiB), held by every GPU the library
  * runs on until the process ends; its address is looked up once per device
  * on the first call there.  Networks whose workspace query
- * (tn_contract_network_workspace) exceeds that size are rejected with
+ * (tn_contract_network_workspace) exceeds that size run their steps whole
+ * (no k-slice partials) when the rest fits, and are otherwise rejected with
  * TN_ERR_UNSUPPORTED before anything runs.  The tile tuner never times
  * candidates inside this call.  Every call on one GPU shares that GPU's
  * array: calls that overlap in time on one GPU (other streams, other host
@@ -437,8 +442,9 @@ int32_t tn_dmrg_eigensolve(const tn_tensor* L, const tn_tensor* R, const tn_tens
  * tn_tune(cache_path, level): sets the level and, when cache_path is not
  * NULL, persists the choices in that text file: entries already in it are
  * loaded now (lines "M N K batch amode bmode cmode prec groups -> choice",
- * choice = tile + 100 log2(k-slices) (k-slices only inside the environment
- * sweep, which holds their scratch), and
+ * choice = tile + 100 log2(k-slices) (k-slices only inside the calls that
+ * hold their scratch: up to 4 in the environment sweeps and inner products,
+ * up to 64 in network steps), and
  * "G step-signature prec -> grouped tile", malformed lines are skipped) and
  * every timed choice made later is appended.
  * NULL keeps the choices in memory only.  Changing the level clears the

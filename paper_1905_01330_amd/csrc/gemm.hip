@@ -1,5 +1,6 @@
 // Contraction GEMM: kernel instantiations, tile selection, autotuner and the
 // grouped launch used for uneven batches of small problems.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -153,46 +154,56 @@ SharedChipScope::~SharedChipScope() { g_shared = prev; }
 // k-slice scratch of the calling thread (SplitKScope), in floats
 static thread_local float* g_splitk = nullptr;
 static thread_local size_t g_splitk_floats = 0;
-
-SplitKScope::SplitKScope(float* scratch, size_t floats) : prev_p(g_splitk), prev_n(g_splitk_floats) {
-  g_splitk = scratch;
-  g_splitk_floats = floats;
-}
-SplitKScope::~SplitKScope() {
-  g_splitk = prev_p;
-  g_splitk_floats = prev_n;
-}
+static thread_local int g_splitk_maxlg = 0;
 
 // A choice is a tile configuration and a k-slice count 2^lg, kept as
 // cfg + 100 lg (lg = 0: the GEMM runs whole).
 static int choice_cfg(int v) { return v % 100; }
 static int choice_lg(int v) { return v / 100; }
-constexpr int kMaxSliceLg = 2;
+constexpr int kMaxSliceLg = 6;
 
-// Whether the GEMM can run as 2^lg k-slices into the scratch: one merged
-// contracted axis (a slice is a pointer offset), no batch (the scale and
-// |C| maximum, if any, are the single entry's and move to the sum kernel),
-// slices of whole 16-k steps and at least 64 long, and room for the 2^lg
-// dense M x N partial results.
+SplitKScope::SplitKScope(float* scratch, size_t floats, int max_lg)
+    : prev_p(g_splitk), prev_n(g_splitk_floats), prev_lg(g_splitk_maxlg) {
+  g_splitk = scratch;
+  g_splitk_floats = floats;
+  g_splitk_maxlg = std::max(0, std::min(max_lg, kMaxSliceLg));
+}
+SplitKScope::~SplitKScope() {
+  g_splitk = prev_p;
+  g_splitk_floats = prev_n;
+  g_splitk_maxlg = prev_lg;
+}
+
+// the most k-slices (log 2) the calling thread's scope allows
+static int max_slice_lg() { return g_splitk ? g_splitk_maxlg : 0; }
+
+// Whether the GEMM can run as 2^lg k-slices into the scratch: the slices
+// cut the outermost contracted axis evenly (a slice is then a pointer
+// offset; with several contracted axes, one that keeps 16-byte alignment),
+// no batch (the scale and |C| maximum, if any, are the single entry's and
+// move to the sum kernel), slices of whole 16-k steps and at least 64 long,
+// and room for the 2^lg dense M x N partial results.
 static bool slices_ok(const GemmDesc& d, int lg) {
   if (lg == 0) return true;
   const int S = 1 << lg;
-  return g_splitk && d.batch == 1 && d.gk.n == 1 && d.K % (16 * S) == 0 && d.K / S >= 64 &&
-         (size_t)S * (size_t)d.M * (size_t)d.N <= g_splitk_floats;
+  if (!g_splitk || lg > max_slice_lg() || d.batch != 1 || d.gk.n < 1 || d.gk.dim[0] % S != 0) return false;
+  const int64_t d0 = d.gk.dim[0] / S;
+  if (d.gk.n > 1 && ((d0 * d.gk.s[0][0]) % 4 != 0 || (d0 * d.gk.s[1][0]) % 4 != 0)) return false;
+  return d.K % (16 * S) == 0 && d.K / S >= 64 && (size_t)S * (size_t)d.M * (size_t)d.N <= g_splitk_floats;
 }
 
 // The slices as a batch of S GEMMs: slice z contracts k in [z K/S, (z+1) K/S)
-// (A and B advanced by K/S steps of their k stride) into the dense M x N
-// partial z of the scratch.
+// (A and B advanced by dim0/S steps of the outermost contracted axis, dim0
+// its extent) into the dense M x N partial z of the scratch.
 static GemmDesc slice_desc(const GemmDesc& d, int S) {
   GemmDesc x = d;
-  const int Ks = d.K / S;
-  x.K = Ks;
-  x.gk.dim[0] = (uint32_t)Ks;
+  const uint32_t d0 = d.gk.dim[0] / (uint32_t)S;
+  x.K = d.K / S;
+  x.gk.dim[0] = d0;
   set_fast_div(x.gk);
   x.batch = S;
-  x.a_bs = (int64_t)Ks * d.gk.s[0][0];
-  x.b_bs = (int64_t)Ks * d.gk.s[1][0];
+  x.a_bs = (int64_t)d0 * d.gk.s[0][0];
+  x.b_bs = (int64_t)d0 * d.gk.s[1][0];
   x.c = g_splitk;
   x.c_bs = (int64_t)d.M * d.N;
   x.a_scale_bits = nullptr;   // applied to the sum (an exact power of two)
@@ -425,7 +436,7 @@ static int heuristic_choice(const GemmDesc& d, int prec) {
   const int c = heuristic_cfg(d, prec);
   if (!g_splitk || g_forced_cfg.load() >= 0) return c;
   const int64_t slots = g_shared ? 128 : 256, tiles = cfg_tiles(d, c);
-  for (int lg = kMaxSliceLg; lg >= 1; --lg)
+  for (int lg = max_slice_lg(); lg >= 1; --lg)
     if (slices_ok(d, lg) && tiles << lg <= slots && d.K >> lg >= 128) return c + 100 * lg;
   return c;
 }
@@ -467,7 +478,7 @@ static int tune_cfg(GemmDesc& d, int32_t prec, int level, hipStream_t st) {
   }
   int best = heuristic_choice(d, prec);
   float best_ms = 1e30f;
-  for (int v = 0; v < kNumCfgs * (kMaxSliceLg + 1); ++v) {
+  for (int v = 0; v < kNumCfgs * (max_slice_lg() + 1); ++v) {
     const int c = v % kNumCfgs, lg = v / kNumCfgs;
     const Cfg& g = kCfgs[c];
     if ((int64_t)g.bm * g.bn > 4ll * d.M * d.N && c != 7) continue;  // mostly padding (32 x 32 always runs)

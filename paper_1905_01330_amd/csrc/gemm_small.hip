@@ -40,15 +40,21 @@ __global__ void __launch_bounds__(256) gemm_small_kernel(const GemmDesc d, int b
   for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < d.M; m += nthreads) {
     int64_t om[2];
     group_offsets<2>(d.gm, (uint32_t)m, om, 0);
+    // the row's K values, all loads in flight before the first is used
+    float av[kSmallK];
+#pragma unroll
+    for (int k = 0; k < kSmallK; ++k) av[k] = k < K ? d.a[om[0] + ka[k]] : 0.0f;
     double acc[kSmallN];
 #pragma unroll
     for (int n = 0; n < kSmallN; ++n) acc[n] = 0.0;
-    for (int k = 0; k < K; ++k) {
-      float a = d.a[om[0] + ka[k]];
-      if (bf16_round) a = small_bf16(a);
 #pragma unroll
-      for (int n = 0; n < kSmallN; ++n)
-        if (n < N) acc[n] += (double)a * (double)sb[k * N + n];
+    for (int k = 0; k < kSmallK; ++k) {
+      if (k < K) {
+        const float a = bf16_round ? small_bf16(av[k]) : av[k];
+#pragma unroll
+        for (int n = 0; n < kSmallN; ++n)
+          if (n < N) acc[n] += (double)a * (double)sb[k * N + n];
+      }
     }
 #pragma unroll
     for (int n = 0; n < kSmallN; ++n)

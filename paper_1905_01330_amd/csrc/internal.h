@@ -70,10 +70,12 @@ struct SharedChipScope {
 // counts beside the tiles; the choice is cached with the tile (the cache
 // value is tile + 100 log2(slices)).
 struct SplitKScope {
-  SplitKScope(float* scratch, size_t floats);
+  // at most 2^max_lg slices a GEMM (capped at 64)
+  SplitKScope(float* scratch, size_t floats, int max_lg = 2);
   ~SplitKScope();
   float* prev_p;
   size_t prev_n;
+  int prev_lg;
 };
 // Householder QR of a column-major m x n FP64 matrix (m >= n, m <= 2048 when
 // householder_qr_fits): factorised in place, with the panels' triangular

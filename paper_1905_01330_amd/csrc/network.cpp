@@ -53,8 +53,16 @@ struct Plan {
   std::vector<Step> steps;
   size_t ws_bytes = 0;
   size_t scratch_off = 0;   // reduction scratch: byte offset in the workspace
+  size_t slices_off = 0;    // k-slice partial results: byte offset, floats
+  size_t slices_floats = 0;
   int final_node = -1;
 };
+
+// k-slices of a network step: up to 64 (a contraction whose result is a few
+// tiles and whose contracted extent is long runs on 64x the workgroups),
+// their partial results capped at 16 MiB
+constexpr int kNetSliceLg = 6;
+constexpr size_t kNetSliceCapFloats = size_t(1) << 22;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -263,7 +271,18 @@ int32_t build_plan(int32_t n_nodes, const tn_tensor* nodes, const int32_t* label
   }
   // then the scratch of the split reductions (few long sums)
   plan.scratch_off = off;
-  plan.ws_bytes = off + kReduceScratchBytes;
+  off = align256(off + kReduceScratchBytes);
+  // then the k-slice partials: 2^kNetSliceLg results of the largest step
+  size_t most = 0;
+  for (auto& st : plan.steps) {
+    if (st.kind != STEP_CONTRACT) continue;
+    size_t cnt = 1;
+    for (int64_t s : plan.nodes[st.result].shape) cnt *= (size_t)s;
+    most = std::max(most, std::min(cnt << kNetSliceLg, kNetSliceCapFloats));
+  }
+  plan.slices_off = off;
+  plan.slices_floats = most;
+  plan.ws_bytes = off + most * 4;
   return TN_OK;
 }
 
@@ -297,6 +316,10 @@ int32_t run_network(const Plan& plan, int32_t n_nodes, const tn_tensor* nodes, t
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   void* scratch = static_cast<char*>(workspace) + plan.scratch_off;
+  // contractions that fill few compute units may run as k-slices
+  SplitKScope slices(plan.slices_floats ? reinterpret_cast<float*>(static_cast<char*>(workspace) + plan.slices_off)
+                                        : nullptr,
+                     plan.slices_floats, kNetSliceLg);
   auto view_of = [&](int id) -> tn_tensor {
     const Node& n = plan.nodes[id];
     if (id == plan.final_node) return fview;
@@ -388,6 +411,11 @@ int32_t tn_contract_network_noalloc(int32_t n_nodes, const tn_tensor* nodes, con
                                     int32_t prec, void* stream) {
   Plan plan;
   TN_TRY(build_plan(n_nodes, nodes, labels, offsets, n_order, order, plan));
+  if (plan.ws_bytes > kNoAllocScratchBytes && plan.slices_off <= kNoAllocScratchBytes) {
+    // no room for the k-slice partials: every step runs whole
+    plan.slices_floats = 0;
+    plan.ws_bytes = plan.slices_off;
+  }
   if (plan.ws_bytes > kNoAllocScratchBytes)
     return fail(TN_ERR_UNSUPPORTED,
                 "network needs %zu bytes of scratch; the library's static scratch holds %zu (use "

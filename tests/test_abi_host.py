@@ -131,12 +131,14 @@ def _network(tensors, labels, order=None):
 
 def test_network_workspace_and_validation():
     # chain a(2,3) - b(3,4) - c(4,5): one intermediate of 2x4 floats (one
-    # 256-byte slot), then the scratch of the split rank-0/1 sums
+    # 256-byte slot), then the scratch of the split rank-0/1 sums, then the
+    # k-slice partials: 64 results of the largest step (2x5 floats; 3x5
+    # when b and c are contracted first)
     ts = [desc([2, 3], A0), desc([3, 4], B0), desc([4, 5], O0)]
     r, nb = _network(ts, [[-1, 0], [0, 1], [1, -2]])
-    assert r == 0 and nb == 256 + L.REDUCE_WORKSPACE_BYTES
+    assert r == 0 and nb == 256 + L.REDUCE_WORKSPACE_BYTES + 64 * 10 * 4
     r, nb = _network(ts, [[-1, 0], [0, 1], [1, -2]], order=[1, 0])
-    assert r == 0 and nb == 256 + L.REDUCE_WORKSPACE_BYTES
+    assert r == 0 and nb == 256 + L.REDUCE_WORKSPACE_BYTES + 64 * 15 * 4
     assert _network(ts, [[-1, 0], [0, 1], [2, -2]])[0] == -1         # label 2 appears once
     assert _network(ts, [[-1, 0], [0, -1], [1, -2]])[0] == -1        # open label repeated
     assert _network(ts, [[-1, 0], [1, 0], [1, -2]])[0] == -2         # dims 3 vs 4 on label 0 ... and 1
@@ -224,7 +226,7 @@ def test_tune_levels_and_cache_file(tmp_path):
     # a cache with valid entries (a whole GEMM, a tile in two k-slices), an
     # out-of-range tile, an out-of-range slice count and a malformed line
     path.write_text("384 320 256 1 1 2 1 2 111 -> 3\n256 768 512 1 1 1 0 2 1111 -> 114\n"
-                    "1 2 3 4 5 6 7 8 9 -> 999\n1 2 3 4 5 6 7 8 9 -> 314\nnot a line\n")
+                    "1 2 3 4 5 6 7 8 9 -> 999\n1 2 3 4 5 6 7 8 9 -> 714\nnot a line\n")
     assert lib.tn_tune(str(path).encode(), 2) == 0
     assert path.read_text().startswith("384 320 256")   # loading never rewrites the file
     assert lib.tn_tune(None, 0) == 0

@@ -74,3 +74,26 @@ def test_exact_order_on_a_small_network():
     for method in ("optimal", "greedy"):
         got, ref, flops, *_ = run(4, 4, False, {1: Z}, "fp32", method=method, seed=3)
         assert abs(got - ref) <= 1e-5 * abs(run(4, 4, False, {}, "fp32", method=method, seed=3)[1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("labels,spec", [
+    ([[-1, 1, 2], [2, 1, -2]], "ijk,kjl->il"),    # two contracted axes whose strides do not merge
+    ([[-1, 1, 2], [1, 2, -2]], "ijk,jkl->il"),    # the same pair merged into one axis
+])
+def test_k_sliced_network_steps(labels, spec, prec):
+    """A step whose result is one or a few tiles (64 x 64) and whose contracted
+    extent is long (4096) runs as k-slices of its outermost contracted axis,
+    the partials summed in slice order.  FP32 accumulation over 4096 terms of
+    unit variance: about u K / sqrt(2) absolute on entries up to about 4 sqrt(K)
+    (split-BF16's six products accumulate in FP32 the same way), well inside
+    5e-6 relative to the largest entry."""
+    rng = np.random.default_rng(21)
+    a = rng.standard_normal((64, 64, 64)).astype(np.float32)
+    b = rng.standard_normal((64, 64, 64)).astype(np.float32)
+    ref = np.einsum(spec, a.astype(np.float64), b.astype(np.float64))
+    out = tn.contract_network([torch.tensor(a, device=DEV), torch.tensor(b, device=DEV)], labels, prec=prec)
+    torch.cuda.synchronize()
+    err = np.abs(out.cpu().double().numpy() - ref).max() / np.abs(ref).max()
+    report(f"k-sliced network step {spec} {prec}", err=float(err))
+    assert err <= 5e-6, err
