@@ -355,7 +355,10 @@ int32_t tn_softmax_xent(const tn_tensor* logits, const int64_t* labels, int32_t 
  * The node `a` (TN_F32 or TN_F64, any strides) is read as the matrix
  * A[(axes 0 .. n_left-1), (axes n_left .. rank-1)] (permute the view to
  * choose the left and right edges) and decomposed as A = U S V^T in FP64 on
- * the GPU (one-sided block Jacobi).  The new bond has at most
+ * the GPU (one-sided block Jacobi; when the longer leg is at most 2048 and
+ * the shorter at least 32, on R^T of a Householder QR of the matrix, whose
+ * columns are closer to orthogonal, with both factors recovered through Q).
+ * The new bond has at most
  * kmax = min(prod left dims, prod right dims) values.
  *
  * tn_split_node_decompose runs the decomposition into `workspace` (size
