@@ -276,6 +276,27 @@ constexpr int64_t lds_padded_rows(int64_t R, int KB) {
   return (R + 2 * (kNT / KB) - 1) / (2 * (kNT / KB)) * (2 * (kNT / KB));
 }
 
+// x from another lane of the same 16-lane row (a DPP move; CTRL is the
+// row-local lane pattern), both 32-bit halves
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// sum over each 16-lane row, in every lane of the row: lane pairs (xor 1),
+// quads (xor 2), mirrored half-rows, mirrored rows; each step adds the same
+// two values in every lane it joins, so all lanes hold the same sum
+__device__ __forceinline__ double row_sum(double x) {
+  x += dpp_move<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_move<0x141>(x);   // row_half_mirror
+  x += dpp_move<0x140>(x);   // row_mirror
+  return x;
+}
+
 // Workgroup barrier for LDS data only: waits for this wave's LDS operations,
 // not for its global loads in flight (a __syncthreads fence waits for both)
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
@@ -370,9 +391,14 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
         be += v.x * v.x + v.y * v.y;
         ga += u.x * v.x + u.y * v.y;
       }
+      // sums over the pair's lanes: within each 16-lane row by DPP moves, then
+      // across rows by lane exchanges (every lane ends with the same values)
+      static_assert(TPP >= 32, "a column pair spans at least two rows of 16 lanes");
+      al = row_sum(al);
+      be = row_sum(be);
+      ga = row_sum(ga);
 #pragma unroll
-      for (int o = TPP / 2; o >= 1; o >>= 1) {
-        if (o >= 64) continue;       // TPP > 64: finished through LDS below
+      for (int o = 16; o < TPP && o < 64; o <<= 1) {
         al += __shfl_xor(al, o, 64);
         be += __shfl_xor(be, o, 64);
         ga += __shfl_xor(ga, o, 64);
@@ -396,11 +422,12 @@ __global__ void __launch_bounds__(kNT) jacobi_lds_kernel(double* W, double* V, i
         }
       }
       double c = 1.0, sn = 0.0;
-      const bool rot = ga != 0.0 && fabs(ga) > tol * sqrt(al * be);
+      // |ga| > tol sqrt(al be), squared (ga^2 <= al be, so no new overflow)
+      const bool rot = ga != 0.0 && ga * ga > (tol * tol) * (al * be);
       if (rot) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        c = 1.0 / sqrt(1.0 + t * t);
+        c = rsqrt(1.0 + t * t);
         sn = t * c;
         rot_sweep = true;
         double2* wa = reinterpret_cast<double2*>(X + a * Rp);
