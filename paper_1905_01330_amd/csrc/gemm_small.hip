@@ -12,6 +12,10 @@ constexpr int kSmallK = 32, kSmallN = 16;
 
 __device__ inline float small_bf16(float x) { return (float)(__bf16)x; }
 
+// PRELOAD: a row's K values are loaded before the first is used (for grids
+// too small to hide one load at a time behind other waves; a full chip
+// hides it, and there the extra registers would cost waves)
+template <bool PRELOAD>
 __global__ void __launch_bounds__(256) gemm_small_kernel(const GemmDesc d, int bf16_round) {
   __shared__ float sb[kSmallK * kSmallN];
   __shared__ int64_t ka[kSmallK];
@@ -40,17 +44,26 @@ __global__ void __launch_bounds__(256) gemm_small_kernel(const GemmDesc d, int b
   for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < d.M; m += nthreads) {
     int64_t om[2];
     group_offsets<2>(d.gm, (uint32_t)m, om, 0);
-    // the row's K values, all loads in flight before the first is used
-    float av[kSmallK];
-#pragma unroll
-    for (int k = 0; k < kSmallK; ++k) av[k] = k < K ? d.a[om[0] + ka[k]] : 0.0f;
     double acc[kSmallN];
 #pragma unroll
     for (int n = 0; n < kSmallN; ++n) acc[n] = 0.0;
+    if constexpr (PRELOAD) {
+      float av[kSmallK];
 #pragma unroll
-    for (int k = 0; k < kSmallK; ++k) {
-      if (k < K) {
-        const float a = bf16_round ? small_bf16(av[k]) : av[k];
+      for (int k = 0; k < kSmallK; ++k) av[k] = k < K ? d.a[om[0] + ka[k]] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < kSmallK; ++k) {
+        if (k < K) {
+          const float a = bf16_round ? small_bf16(av[k]) : av[k];
+#pragma unroll
+          for (int n = 0; n < kSmallN; ++n)
+            if (n < N) acc[n] += (double)a * (double)sb[k * N + n];
+        }
+      }
+    } else {
+      for (int k = 0; k < K; ++k) {
+        float a = d.a[om[0] + ka[k]];
+        if (bf16_round) a = small_bf16(a);
 #pragma unroll
         for (int n = 0; n < kSmallN; ++n)
           if (n < N) acc[n] += (double)a * (double)sb[k * N + n];
@@ -79,7 +92,11 @@ int32_t launch_gemm_small(const GemmDesc& d0, int32_t prec, hipStream_t st) {
   }
   int64_t blocks = (d.M + 255) / 256;
   blocks = blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks);
-  hipLaunchKernelGGL(gemm_small_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, prec == TN_PREC_BF16 ? 1 : 0);
+  const int bf = prec == TN_PREC_BF16 ? 1 : 0;
+  if (blocks < 256)
+    hipLaunchKernelGGL(gemm_small_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, d, bf);
+  else
+    hipLaunchKernelGGL(gemm_small_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, d, bf);
   return hip_check(hipGetLastError(), "small gemm launch");
 }
 
