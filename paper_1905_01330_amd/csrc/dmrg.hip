@@ -124,6 +124,8 @@ __global__ void __launch_bounds__(256) tridiag_min_kernel(const double* alpha, c
   __shared__ int ab[P / 2][2];
   __shared__ int m_eff;
   __shared__ double big;
+  __shared__ int rotated;
+  __shared__ double nrm;
   const int tid = threadIdx.x;
   if (tid == 0) {
     int me = m;
@@ -133,9 +135,10 @@ __global__ void __launch_bounds__(256) tridiag_min_kernel(const double* alpha, c
         break;
       }
     m_eff = me;
-    double s = 1.0;
+    double s = 0.0;
     for (int j = 0; j < me; ++j) s += fabs(alpha[j]) + (j + 1 < me ? 2.0 * fabs(beta[j]) : 0.0);
-    big = 4.0 * s;   // above every eigenvalue of the kept block (Gershgorin)
+    nrm = s;                 // bounds |T| of the kept block from above
+    big = 4.0 * (s + 1.0);   // above every eigenvalue of the kept block (Gershgorin)
   }
   __syncthreads();
   for (int e = tid; e < P * P; e += 256) {
@@ -152,7 +155,13 @@ __global__ void __launch_bounds__(256) tridiag_min_kernel(const double* alpha, c
     Z[i][j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
+  // sweeps until one rotates no pair (at most 20): a pair counts as
+  // diagonal once |T_ab| <= 2^-60 |T|, which moves no eigenvalue by more
+  // than that
+  const double thr = 0x1p-60 * nrm;
   for (int sweep = 0; sweep < 20; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
     for (int step = 0; step < P - 1; ++step) {
       if (tid < P / 2) {
         int a, b;
@@ -170,7 +179,8 @@ __global__ void __launch_bounds__(256) tridiag_min_kernel(const double* alpha, c
         }
         const double app = T[a][a], aqq = T[b][b], apq = T[a][b];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
+        if (fabs(apq) > thr) {
+          rotated = 1;
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -204,6 +214,8 @@ __global__ void __launch_bounds__(256) tridiag_min_kernel(const double* alpha, c
       }
       __syncthreads();
     }
+    if (rotated == 0) break;   // read by every thread after the last barrier
+    __syncthreads();           // before thread 0 clears it for the next sweep
   }
   if (tid == 0) {
     int best = 0;
