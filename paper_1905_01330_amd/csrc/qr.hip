@@ -127,6 +127,49 @@ constexpr int kQrNb = 16;         // panel width
 constexpr int kQrCb = 4;          // trailing columns per workgroup
 constexpr int kQrWaves = kQrThreads / 64;
 
+// x from lane (this lane xor M) of the wavefront.  Within a 16-lane row (M <
+// 16) a DPP move on each 32-bit half: quad permutations for M = 1, 2, the
+// row rotation by 8 for M = 8, and for M = 4 the rotation by 4 or by 12 as
+// the lane's bit 2 is set or clear; across rows a lane exchange through the
+// LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ double qr_dpp(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+template <int M>
+__device__ __forceinline__ double qr_xor_lane(double x) {
+  if constexpr (M == 1) return qr_dpp<0xB1>(x);         // quad_perm [1, 0, 3, 2]
+  else if constexpr (M == 2) return qr_dpp<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  else if constexpr (M == 4) {
+    // row_ror n: lane i reads lane (i - n) mod 16 of its row
+    const double below = qr_dpp<0x124>(x);              // row_ror 4: lane i - 4
+    const double above = qr_dpp<0x12C>(x);              // row_ror 12: lane i + 4
+    return (threadIdx.x & 4) ? below : above;
+  } else if constexpr (M == 8) return qr_dpp<0x128>(x);  // row_ror 8: lane i xor 8
+  else return __shfl_xor(x, M, 64);
+}
+
+// x of lane L (a constant) in every lane
+template <int L>
+__device__ __forceinline__ double qr_read_lane(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, L);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), L);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+template <int NV, int I = 0>
+__device__ __forceinline__ void qr_broadcast(double t, double (&v)[NV]) {
+  if constexpr (I < NV) {
+    v[I] = qr_read_lane<I>(t);
+    qr_broadcast<NV, I + 1>(t, v);
+  }
+}
+
 // Wavefront reduce-scatter of N partial values (N a power of two <= 64):
 // lane l returns the sum over the 64 lanes of value l % N.  Each halving step
 // sends one half of the remaining values to the partner lane and keeps the
@@ -139,9 +182,18 @@ __device__ __forceinline__ void qr_halve(double (&v)[N], int lane) {
     for (int i = 0; i < H; ++i) {
       const double send = up ? v[i] : v[i + H];
       const double keep = up ? v[i + H] : v[i];
-      v[i] = keep + __shfl_xor(send, H, 64);
+      v[i] = keep + qr_xor_lane<H>(send);
     }
     qr_halve<N, H / 2>(v, lane);
+  }
+}
+
+// r summed over the lane groups that differ in bits N, 2N, ... 32
+template <int MK>
+__device__ __forceinline__ void qr_xor_tail(double& r) {
+  if constexpr (MK < 64) {
+    r += qr_xor_lane<MK>(r);
+    qr_xor_tail<MK * 2>(r);
   }
 }
 
@@ -150,8 +202,7 @@ __device__ inline double qr_reduce_scatter(double (&v)[N]) {
   const int lane = threadIdx.x & 63;
   qr_halve<N, N / 2>(v, lane);
   double r = v[0];
-#pragma unroll
-  for (int mk = N; mk < 64; mk *= 2) r += __shfl_xor(r, mk, 64);
+  qr_xor_tail<N>(r);
   return r;
 }
 
@@ -177,8 +228,7 @@ __device__ inline void qr_block_sum(double (&v)[NV], double (*red)[kQrWaves * 64
 #pragma unroll
     for (int wv = 0; wv < kQrWaves; ++wv) t += red[buf][wv * P + lane];
   }
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = __shfl(t, i, 64);
+  qr_broadcast<NV>(t, v);
   buf ^= 1;
 }
 
