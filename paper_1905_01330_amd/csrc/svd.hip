@@ -556,26 +556,15 @@ __global__ void column_norm_kernel(const double* W, int64_t R, double* sigma) {
 }
 
 // order[t] = the column of the t-th largest singular value (ties: lower column first)
-__global__ void __launch_bounds__(256) rank_kernel(const double* sigma, int n, int* order) {
-  constexpr int kChunk = 2048;   // values staged in LDS at a time
-  __shared__ double sh[kChunk];
-  // the block's threads take columns j0 + tid (the loop bound is the same
-  // for the whole block, so every thread reaches the barriers)
-  for (int j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
-    const int j = j0 + threadIdx.x;
-    const double sj = j < n ? sigma[j] : 0.0;
+__global__ void rank_kernel(const double* sigma, int n, int* order) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const double sj = sigma[j];
     int rank = 0;
-    for (int i0 = 0; i0 < n; i0 += kChunk) {
-      const int cnt = min(kChunk, n - i0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < cnt; e += blockDim.x) sh[e] = sigma[i0 + e];
-      __syncthreads();
-      for (int i = 0; i < cnt; ++i) {
-        const double si = sh[i];
-        rank += (si > sj || (si == sj && i0 + i < j)) ? 1 : 0;
-      }
+    for (int i = 0; i < n; ++i) {
+      const double si = sigma[i];
+      rank += (si > sj || (si == sj && i < j)) ? 1 : 0;
     }
-    if (j < n) order[rank] = j;
+    order[rank] = j;
   }
 }
 
