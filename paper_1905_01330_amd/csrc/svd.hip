@@ -556,15 +556,21 @@ __global__ void column_norm_kernel(const double* W, int64_t R, double* sigma) {
 }
 
 // order[t] = the column of the t-th largest singular value (ties: lower column first)
-__global__ void rank_kernel(const double* sigma, int n, int* order) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+// one wavefront per column j: its lanes count the larger values (ties by
+// index) over strided parts of sigma, then add their counts
+__global__ void __launch_bounds__(256) rank_kernel(const double* sigma, int n, int* order) {
+  const int lane = threadIdx.x & 63;
+  const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+  for (int j = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); j < n; j += nw) {
     const double sj = sigma[j];
     int rank = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = lane; i < n; i += 64) {
       const double si = sigma[i];
       rank += (si > sj || (si == sj && i < j)) ? 1 : 0;
     }
-    order[rank] = j;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) rank += __shfl_xor(rank, o, 64);
+    if (lane == 0) order[rank] = j;
   }
 }
 
@@ -891,7 +897,7 @@ int32_t tn_split_node_decompose(const tn_tensor* a, int32_t n_left, int32_t max_
       // columns in descending order of their norms: the blocks of a sweep then
       // pair columns of similar size first (fewer sweeps on graded spectra)
       hipLaunchKernelGGL(column_norm_kernel, dim3((unsigned)g.Cp), dim3(kNT), 0, st, M, rows, sigma);
-      hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((g.Cp + 255) / 256)), dim3(256), 0, st, sigma, (int)g.Cp, perm);
+      hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((g.Cp + 3) / 4)), dim3(256), 0, st, sigma, (int)g.Cp, perm);
       hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, ctl);
       for (int r = 0; r < g.nb - 1; ++r) {
         const dim3 grid(g.nb / 2), blk(kNT);
@@ -942,7 +948,7 @@ int32_t tn_split_node_decompose(const tn_tensor* a, int32_t n_left, int32_t max_
     TN_TRY(hip_check(hipGetLastError(), "svd precondition"));
   }
   hipLaunchKernelGGL(column_norm_kernel, dim3((unsigned)g.Cp), dim3(kNT), 0, st, W, g.R, sigma);
-  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((g.Cp + 255) / 256)), dim3(256), 0, st, sigma, (int)g.Cp, order);
+  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((g.Cp + 3) / 4)), dim3(256), 0, st, sigma, (int)g.Cp, order);
   hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(64), 0, st, sigma, order, (int)g.C, max_singular_values,
                      max_truncation_err, ctl + 1);
   TN_TRY(hip_check(hipGetLastError(), "singular values"));
