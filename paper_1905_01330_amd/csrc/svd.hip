@@ -708,6 +708,10 @@ int32_t svd_geometry(const tn_tensor* a, int32_t n_left, SvdGeom& g) {
   g.lds = false;
   for (int w : {8, 4, 2, 1}) {
     if (lds_padded_rows(jr, w) > lds_rows(w)) continue;
+    // width 8's fifteen dependent steps a round cost more than the model
+    // holds at a few hundred rows and up: width 4 measured faster at 512
+    // rows (the chi = 256 DMRG split) and at 1000
+    if (w == 8 && jr >= 384) continue;
     g.lds = true;
     int nbw = (int)((g.C + w - 1) / w);
     nbw = nbw < 2 ? 2 : nbw + (nbw % 2);
